@@ -1,0 +1,156 @@
+/*
+ * bz.h -- C ABI of libbz: the Brouwer-Zimmermann minimum distance of a binary
+ * linear code on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv:1911.08963, Sec. 2.1 and Alg. 1. For an [n, k] code with
+ * generator matrix G, find disjoint information sets S_1..S_{m_f} (plus a
+ * leftover set S_m of rank k_m < k), put G in systematic form Gamma_j on each,
+ * and for g = 1, 2, ... enumerate every sum of g rows of every Gamma_j. The
+ * smallest weight seen is an upper bound U on d; after each completed
+ * (Gamma_j, g) the enumerated sums certify a lower bound L. The search stops
+ * once L >= U, and then d = U.
+ *
+ * Conventions for every call:
+ *  - All functions return a bz_status: 0 = success, negative = error.
+ *  - On error, no output is marked valid (d = 0).
+ *  - bz_last_error() holds a thread-local message describing the last error.
+ *  - Bit layout: matrices are row-major uint64 words, LSB first. Coordinate c
+ *    of row i is bit (c % 64) of word [i * ld_words + c / 64]. Bits at
+ *    positions >= n are ignored on input and zero on output.
+ *  - Host pointers are read or written only during the call. The library keeps
+ *    no caller pointer after it returns.
+ *  - Device work runs on the caller's HIP stream (bz_opts.hip_stream, NULL = the
+ *    null stream). Calls are synchronous: the results are in caller memory when
+ *    they return. A prepared bz_code is immutable: any number of threads may
+ *    search it concurrently, each on its own stream with its own workspace.
+ *  - Limits: n <= BZ_MAX_N. Every level searched must have C(k, g) < 2^63
+ *    (BZ_ELIMIT otherwise).
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BZ_MAX_N 256
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_EINVAL = -1,     /* a null pointer, a size out of range, an unknown flag   */
+    BZ_ERANK = -2,      /* the k rows of G are linearly dependent                  */
+    BZ_ENOMEM = -3,     /* host or device allocation failed, or workspace too small */
+    BZ_EDEVICE = -4,    /* a HIP call failed (bz_last_error names it)              */
+    BZ_ELIMIT = -5,     /* C(k,g) >= 2^63, max_level reached, or stats buffer full */
+    BZ_ECANCELED = -6,  /* the caller's cancel word became nonzero                 */
+    BZ_EBUSY = -7       /* the server has no free slot                             */
+} bz_status;
+
+typedef struct bz_code bz_code;   /* opaque; immutable after bz_prepare */
+
+/* Column-permutation search used to find the information sets (Sec. 2.2,
+ * the paragraph on computing the Gamma matrices). perm_trials = 0 or 1
+ * scans the columns in their natural order. */
+typedef struct {
+    uint32_t perm_trials;
+    uint32_t _reserved;
+    uint64_t perm_seed;
+} bz_prepare_opts;
+
+/* Sec. 2.1, information sets and the systematic matrices Gamma_j.
+ * Copies G (k rows of ld_words uint64, layout above); the caller keeps G.
+ * Finds the information sets greedily: S_1 is the first basis in column order,
+ * S_2 the first basis of the remaining columns, and so on, while the remaining
+ * columns still have rank k. The last columns have rank k_m < k. Gamma_j is
+ * the reduced echelon form of G with S_j's columns first. Gamma_j's
+ * non-identity columns are uploaded to the current HIP device.
+ * Errors: EINVAL (G or out null, k == 0, k > n, n > BZ_MAX_N,
+ * ld_words < ceil(n/64)); ERANK (rank(G) < k); ENOMEM; EDEVICE. */
+bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_words,
+                     const bz_prepare_opts *opts /* nullable */, bz_code **out);
+
+typedef struct {
+    uint32_t n, k;
+    uint32_t num_full;      /* m_f: number of full-rank disjoint information sets   */
+    uint32_t partial_rank;  /* k_m: rank of the leftover columns (0 = no Gamma_m)   */
+    uint32_t W_full;        /* 32-bit words per device row of a full-rank Gamma_j   */
+    uint32_t W_partial;     /* the same for Gamma_m (0 if absent)                    */
+} bz_code_info;
+
+/* set_of_column (nullable, n entries): index j of the set holding column c, or -1. */
+bz_status bz_code_get_info(const bz_code *c, bz_code_info *out, int32_t *set_of_column);
+
+/* Host copy of Gamma_j (k rows of ld_words uint64, original column order). */
+bz_status bz_code_get_gamma(const bz_code *c, uint32_t matrix, uint64_t *rows, uint32_t ld_words);
+
+void bz_free(bz_code *c);
+
+/* Search flags. */
+enum {
+    BZ_F_STATS = 1u,        /* record per-(Gamma_j, g) minimum and count; no exit inside a task */
+    BZ_F_LEVEL_STOP = 2u,   /* check L >= U once per level (Alg. 1 as printed)                 */
+    BZ_F_NO_WITNESS = 4u    /* skip witness recovery                                           */
+};
+
+typedef struct {
+    uint32_t flags;
+    uint32_t max_level;         /* 0 = no limit; otherwise stop (BZ_ELIMIT) after this level */
+    void *hip_stream;           /* hipStream_t, or NULL for the null stream                  */
+    void *workspace;            /* caller device memory, or NULL: the library allocates     */
+    size_t workspace_bytes;
+    volatile const uint32_t *cancel;   /* host-visible word; nonzero cancels (nullable)      */
+    uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8); 0 = tuned choice    */
+    uint32_t heads_per_tile;    /* head steps per wave tile; 0 = tuned choice                */
+} bz_opts;
+
+typedef struct {
+    uint16_t matrix, level;     /* j (0-based; the partial Gamma_m is j = m_f) and g        */
+    uint32_t min_weight;        /* min wt(c Gamma_j) over wt(c) = g                          */
+    uint64_t count_at_min;      /* number of c reaching it (BZ_F_STATS only, else 0)         */
+    uint64_t combinations;      /* C(k, g) for a completed task                              */
+} bz_level_stat;
+
+typedef struct {
+    uint32_t d;                 /* minimum distance (0 unless status is BZ_OK)               */
+    uint32_t lower_bound;       /* last certified L                                          */
+    uint32_t upper_bound;       /* U at the end                                              */
+    uint32_t last_level;        /* last level g entered                                      */
+    uint64_t combinations;      /* row combinations enumerated                               */
+    uint64_t *witness;          /* caller buffer of ceil(n/64) words, or NULL                */
+    bz_level_stat *stats;       /* caller buffer of stats_cap entries, or NULL               */
+    uint32_t stats_cap;
+    uint32_t stats_len;         /* tasks completed (may exceed stats_cap: then BZ_ELIMIT)    */
+    uint32_t launches;          /* enumeration kernel launches                               */
+    uint32_t _pad;
+    double prepare_s;           /* host seconds in bz_prepare (filled by the batch call)     */
+    double search_s;            /* host wall seconds of the search                           */
+    double kernel_s;            /* summed device time of the enumeration launches            */
+} bz_result;
+
+/* Device bytes the library needs for these codes under these options. */
+bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opts *o, size_t *bytes);
+
+/* Alg. 1 on one code, the check after every Gamma_j by default.
+ * Level g of Gamma_j is one launch of the enumeration kernel. Each wave takes
+ * equal-sized tiles of the combination space (Sec. 3.1 explains why tasks
+ * should cost the same), keeps the running minimum in registers, and ends each
+ * tile with one atomic. The witness is the codeword of weight d that the
+ * recovery kernel re-finds in the winning tile. */
+bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
+
+/* Many codes at once: one persistent launch drains a device queue of
+ * (code, Gamma_j, g, tile) work for all of them. res[i] and per_code[i] belong
+ * to codes[i]. Returns the first per-code error, or BZ_OK. */
+bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
+                                bz_result *res, bz_status *per_code);
+
+const char *bz_status_str(bz_status s);
+const char *bz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BZ_H */

@@ -1,0 +1,319 @@
+"""Python binding of libbz (include/bz.h): argument marshalling only.
+
+Every step of the search runs in libbz: the host preparation in its C++ part
+and the enumeration, reductions and witness recovery in its HIP kernels.
+PyTorch provides the device workspace and the stream. Importing this module
+loads libbz.so; it raises if the library has not been built
+(``python -m paper_1911_08963_amd.build``). There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbz.so")
+
+BZ_OK, BZ_EINVAL, BZ_ERANK, BZ_ENOMEM, BZ_EDEVICE, BZ_ELIMIT, BZ_ECANCELED, BZ_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7
+BZ_F_STATS, BZ_F_LEVEL_STOP, BZ_F_NO_WITNESS = 1, 2, 4
+BZ_MAX_N = 256
+
+P = ctypes.POINTER
+
+
+class PrepareOpts(ctypes.Structure):
+    _fields_ = [("perm_trials", ctypes.c_uint32), ("_reserved", ctypes.c_uint32),
+                ("perm_seed", ctypes.c_uint64)]
+
+
+class CodeInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("k", ctypes.c_uint32), ("num_full", ctypes.c_uint32),
+                ("partial_rank", ctypes.c_uint32), ("W_full", ctypes.c_uint32),
+                ("W_partial", ctypes.c_uint32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("max_level", ctypes.c_uint32),
+                ("hip_stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("cancel", P(ctypes.c_uint32)),
+                ("slots_per_lane", ctypes.c_uint32), ("heads_per_tile", ctypes.c_uint32)]
+
+
+class LevelStat(ctypes.Structure):
+    _fields_ = [("matrix", ctypes.c_uint16), ("level", ctypes.c_uint16),
+                ("min_weight", ctypes.c_uint32), ("count_at_min", ctypes.c_uint64),
+                ("combinations", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_uint32), ("lower_bound", ctypes.c_uint32),
+                ("upper_bound", ctypes.c_uint32), ("last_level", ctypes.c_uint32),
+                ("combinations", ctypes.c_uint64), ("witness", P(ctypes.c_uint64)),
+                ("stats", P(LevelStat)), ("stats_cap", ctypes.c_uint32),
+                ("stats_len", ctypes.c_uint32), ("launches", ctypes.c_uint32),
+                ("_pad", ctypes.c_uint32), ("prepare_s", ctypes.c_double),
+                ("search_s", ctypes.c_double), ("kernel_s", ctypes.c_double)]
+
+
+class DebugRect(ctypes.Structure):
+    _fields_ = [("lane_off", ctypes.c_uint32), ("lane_n", ctypes.c_uint32),
+                ("lane_t", ctypes.c_uint32), ("head_off", ctypes.c_uint32),
+                ("head_n", ctypes.c_uint32), ("head_t", ctypes.c_uint32),
+                ("_reserved0", ctypes.c_uint32), ("_reserved1", ctypes.c_uint32),
+                ("lane_count", ctypes.c_uint64), ("head_count", ctypes.c_uint64),
+                ("tile_begin", ctypes.c_uint64), ("lane_blocks", ctypes.c_uint64),
+                ("head_blocks", ctypes.c_uint64), ("_reserved2", ctypes.c_uint64)]
+
+
+class BZError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _signatures(lib):
+    vp = ctypes.c_void_p
+    u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "bz_prepare": ([P(u64), u32, u32, u32, P(PrepareOpts), P(vp)], ctypes.c_int),
+        "bz_code_get_info": ([vp, P(CodeInfo), P(ctypes.c_int32)], ctypes.c_int),
+        "bz_code_get_gamma": ([vp, u32, P(u64), u32], ctypes.c_int),
+        "bz_free": ([vp], None),
+        "bz_workspace_bytes": ([P(vp), u32, P(Opts), P(ctypes.c_size_t)], ctypes.c_int),
+        "bz_min_distance": ([vp, P(Opts), P(Result)], ctypes.c_int),
+        "bz_min_distance_batch": ([P(vp), u32, P(Opts), P(Result), P(ctypes.c_int)], ctypes.c_int),
+        "bz_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "bz_last_error": ([], ctypes.c_char_p),
+        "bz_debug_prepare_host": ([P(u64), u32, u32, u32, P(u32), P(u32), P(ctypes.c_int32),
+                                   P(u64), u32, P(u32), ctypes.c_size_t], ctypes.c_int),
+        "bz_debug_plan_level": ([u32, u32, u32, u32, u64, P(DebugRect), u32, P(u32), P(u64),
+                                 P(u32)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libbz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libbz.so is not built ({LIB_PATH}); run python -m paper_1911_08963_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        _signatures(L)
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != BZ_OK:
+        raise BZError(st, lib().bz_last_error().decode() or lib().bz_status_str(st).decode())
+
+
+def _words(G) -> np.ndarray:
+    G = np.ascontiguousarray(G, dtype=np.uint64)
+    if G.ndim != 2:
+        raise ValueError("G must be a (k, ld) uint64 array")
+    return G
+
+
+class Code:
+    """A prepared code (bz_prepare): information sets and Gamma_j on the current device."""
+
+    def __init__(self, G, n: int, perm_trials: int = 0, perm_seed: int = 0):
+        G = _words(G)
+        k, ld = G.shape
+        self.n, self.k = int(n), int(k)
+        h = ctypes.c_void_p()
+        po = PrepareOpts(perm_trials, 0, perm_seed)
+        _check(lib().bz_prepare(G.ctypes.data_as(P(ctypes.c_uint64)), k, n, ld, ctypes.byref(po),
+                                ctypes.byref(h)))
+        self._h = h
+        info = CodeInfo()
+        soc = np.zeros(n, dtype=np.int32)
+        _check(lib().bz_code_get_info(h, ctypes.byref(info), soc.ctypes.data_as(P(ctypes.c_int32))))
+        self.num_full, self.partial_rank = info.num_full, info.partial_rank
+        self.W_full, self.W_partial = info.W_full, info.W_partial
+        self.set_of_column = soc
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nsets(self) -> int:
+        return self.num_full + (1 if self.partial_rank else 0)
+
+    def gamma(self, j: int) -> np.ndarray:
+        ld = (self.n + 63) // 64
+        out = np.zeros((self.k, ld), dtype=np.uint64)
+        _check(lib().bz_code_get_gamma(self._h, j, out.ctypes.data_as(P(ctypes.c_uint64)), ld))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bz_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class SearchResult:
+    status: int
+    d: int
+    lower_bound: int
+    upper_bound: int
+    last_level: int
+    combinations: int
+    witness: np.ndarray
+    stats: list = field(default_factory=list)   # (matrix, level, min_weight, count_at_min, combinations)
+    launches: int = 0
+    prepare_s: float = 0.0
+    search_s: float = 0.0
+    kernel_s: float = 0.0
+
+
+_ws_cache = {}
+
+
+def workspace_bytes() -> int:
+    b = ctypes.c_size_t()
+    _check(lib().bz_workspace_bytes(None, 0, None, ctypes.byref(b)))
+    return b.value
+
+
+def _workspace(device, nbytes):
+    import torch
+    key = (str(device), nbytes)
+    t = _ws_cache.get(key)
+    if t is None:
+        t = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _ws_cache[key] = t
+    return t
+
+
+def _opts(flags, max_level, stream, ws, cancel, slots, heads) -> Opts:
+    o = Opts()
+    o.flags = flags
+    o.max_level = max_level
+    o.hip_stream = stream
+    o.workspace = ws.data_ptr() if ws is not None else None
+    o.workspace_bytes = ws.numel() if ws is not None else 0
+    o.cancel = cancel
+    o.slots_per_lane = slots
+    o.heads_per_tile = heads
+    return o
+
+
+def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
+                 witness: bool = True, max_level: int = 0, slots_per_lane: int = 0,
+                 heads_per_tile: int = 0, stats_cap: int = 4096, stream=None,
+                 cancel=None, raise_on_error: bool = True) -> SearchResult:
+    """bz_min_distance on the current torch stream, with a torch-allocated workspace."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    ws = _workspace(dev, workspace_bytes())
+    flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
+        (0 if witness else BZ_F_NO_WITNESS)
+    o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
+    wit = np.zeros(4, dtype=np.uint64)
+    st_buf = (LevelStat * stats_cap)()
+    r = Result()
+    r.witness = wit.ctypes.data_as(P(ctypes.c_uint64))
+    r.stats = st_buf
+    r.stats_cap = stats_cap
+    st = lib().bz_min_distance(code.handle, ctypes.byref(o), ctypes.byref(r))
+    if st != BZ_OK and raise_on_error:
+        _check(st)
+    out = SearchResult(st, r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,
+                       wit[: (code.n + 63) // 64].copy(), [], r.launches, r.prepare_s, r.search_s,
+                       r.kernel_s)
+    for i in range(min(r.stats_len, stats_cap)):
+        s = st_buf[i]
+        out.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
+    return out
+
+
+def min_distance_batch(codes, *, stats: bool = False, witness: bool = True, stream=None,
+                       stats_cap: int = 512, slots_per_lane: int = 0, heads_per_tile: int = 0):
+    """bz_min_distance_batch: returns (list of SearchResult, list of status)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    cnt = len(codes)
+    handles = (ctypes.c_void_p * cnt)(*[c.handle.value for c in codes])
+    flags = (BZ_F_STATS if stats else 0) | (0 if witness else BZ_F_NO_WITNESS)
+    nbytes = ctypes.c_size_t()
+    o = _opts(flags, 0, stream.cuda_stream, None, None, slots_per_lane, heads_per_tile)
+    _check(lib().bz_workspace_bytes(handles, cnt, ctypes.byref(o), ctypes.byref(nbytes)))
+    ws = _workspace(dev, nbytes.value)
+    o = _opts(flags, 0, stream.cuda_stream, ws, None, slots_per_lane, heads_per_tile)
+    res = (Result * cnt)()
+    wits = np.zeros((cnt, 4), dtype=np.uint64)
+    stb = [(LevelStat * stats_cap)() for _ in range(cnt)]
+    for i in range(cnt):
+        res[i].witness = wits[i].ctypes.data_as(P(ctypes.c_uint64))
+        res[i].stats = stb[i]
+        res[i].stats_cap = stats_cap
+    per = (ctypes.c_int * cnt)()
+    lib().bz_min_distance_batch(handles, cnt, ctypes.byref(o), res, per)
+    outs = []
+    for i in range(cnt):
+        r = res[i]
+        o_ = SearchResult(per[i], r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,
+                          wits[i][: (codes[i].n + 63) // 64].copy(), [], r.launches, r.prepare_s,
+                          r.search_s, r.kernel_s)
+        for t in range(min(r.stats_len, stats_cap)):
+            s = stb[i][t]
+            o_.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
+        outs.append(o_)
+    return outs, [per[i] for i in range(cnt)]
+
+
+# ---------------------------------------------------------------- host-only inspection
+
+def prepare_host(G, n: int):
+    """bz_debug_prepare_host: (set_of_column, m_f, k_m, gamma rows, packed words)."""
+    G = _words(G)
+    k, ld = G.shape
+    mf, km = ctypes.c_uint32(), ctypes.c_uint32()
+    soc = np.zeros(n, dtype=np.int32)
+    cap = (n + 1) * k
+    gam = np.zeros((cap, ld), dtype=np.uint64)
+    packed = np.zeros(cap * (BZ_MAX_N // 32), dtype=np.uint32)
+    _check(lib().bz_debug_prepare_host(G.ctypes.data_as(P(ctypes.c_uint64)), k, n, ld,
+                                       ctypes.byref(mf), ctypes.byref(km),
+                                       soc.ctypes.data_as(P(ctypes.c_int32)),
+                                       gam.ctypes.data_as(P(ctypes.c_uint64)), cap,
+                                       packed.ctypes.data_as(P(ctypes.c_uint32)), packed.size))
+    nsets = mf.value + (1 if km.value else 0)
+    return soc, mf.value, km.value, gam[: nsets * k].copy(), packed
+
+
+def plan_level(k: int, g: int, slots: int = 8, heads_per_tile: int = 0, target_tiles: int = 1 << 17):
+    """bz_debug_plan_level: (list of rect dicts, total_tiles, heads_per_tile)."""
+    cap = 16384
+    rects = (DebugRect * cap)()
+    nr, tt, hu = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+    _check(lib().bz_debug_plan_level(k, g, slots, heads_per_tile, target_tiles, rects, cap,
+                                     ctypes.byref(nr), ctypes.byref(tt), ctypes.byref(hu)))
+    out = []
+    for i in range(nr.value):
+        r = rects[i]
+        out.append({f: getattr(r, f) for f, _ in DebugRect._fields_ if not f.startswith("_")})
+    return out, tt.value, hu.value

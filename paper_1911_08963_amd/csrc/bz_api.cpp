@@ -1,0 +1,430 @@
+// The C ABI of libbz (include/bz.h): preparation, the level driver of Alg. 1
+// (arXiv:1911.08963) for one code, witness recovery, and errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bz_internal.h"
+#include "bz_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+bz_status fail(bz_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define BZ_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return fail(BZ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Per-device constants: the binomial table and the compute-unit count.
+struct DeviceConst {
+    uint64_t *binom = nullptr;
+    int cus = 0;
+};
+std::mutex g_mu;
+std::map<int, DeviceConst> g_devconst;
+
+bz_status device_const(int dev, DeviceConst &out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_devconst.find(dev);
+    if (it != g_devconst.end()) { out = it->second; return BZ_OK; }
+    DeviceConst dc;
+    BZ_HIP(hipDeviceGetAttribute(&dc.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<uint64_t> tab((size_t)bz::kBinomRows * (bz::kBinomT + 1));
+    for (uint32_t x = 0; x < (uint32_t)bz::kBinomRows; ++x)
+        for (uint32_t y = 0; y <= (uint32_t)bz::kBinomT; ++y)
+            tab[(size_t)x * (bz::kBinomT + 1) + y] = bz::binom_sat(x, y);
+    BZ_HIP(hipMalloc(&dc.binom, tab.size() * sizeof(uint64_t)));
+    BZ_HIP(hipMemcpy(dc.binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    g_devconst[dev] = dc;
+    out = dc;
+    return BZ_OK;
+}
+
+// Workspace layout of one search (bytes).
+constexpr size_t kWsTask = 0;          // key, stats, ncomb, tile counter (u64 each)
+constexpr size_t kWsRecover = 64;      // flag, len (u32), codeword (4 x u64)
+constexpr size_t kWsIndices = 128;     // up to 256 u32 row indices
+constexpr size_t kWsRecoverRect = 1280;
+constexpr size_t kWsRects = 4096;
+constexpr size_t kMaxRects = 16384;
+constexpr size_t kWsBytes = kWsRects + kMaxRects * sizeof(bz::Rect);
+
+uint32_t default_slots(uint32_t W) { return W <= 4 ? 8u : 4u; }
+
+// Lower bound certified once Gamma_0..Gamma_j are done at level g and the
+// later matrices at level g-1 (j == m_f is the partial matrix).
+uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t k) {
+    if (j >= m_f) {
+        int64_t extra = k_m ? (int64_t)g + 1 - k + k_m : 0;
+        return m_f * (g + 1) + (uint32_t)std::max<int64_t>(0, extra);
+    }
+    int64_t extra = k_m ? (int64_t)g - k + k_m : 0;
+    return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)std::max<int64_t>(0, extra);
+}
+
+struct Best {
+    bool have = false;
+    uint32_t j = 0, g = 0, slots = 0, ht = 0;
+    uint64_t tile = 0;
+    bz::Rect rect{};
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *bz_status_str(bz_status s) {
+    switch (s) {
+    case BZ_OK: return "ok";
+    case BZ_EINVAL: return "invalid argument";
+    case BZ_ERANK: return "generator matrix rank < k";
+    case BZ_ENOMEM: return "out of memory";
+    case BZ_EDEVICE: return "device error";
+    case BZ_ELIMIT: return "limit reached";
+    case BZ_ECANCELED: return "canceled";
+    case BZ_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char *bz_last_error(void) { return g_err.c_str(); }
+
+bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_words,
+                     const bz_prepare_opts *opts, bz_code **out) {
+    if (!out) return fail(BZ_EINVAL, "out is null");
+    *out = nullptr;
+    double t0 = now_s();
+    std::unique_ptr<bz_code> c(new (std::nothrow) bz_code());
+    if (!c) return fail(BZ_ENOMEM, "host allocation");
+    std::string err;
+    bz_status st = bz::prepare_host(G, k, n, ld_words, opts, *c, err);
+    if (st != BZ_OK) return fail(st, err);
+    BZ_HIP(hipGetDevice(&c->device));
+    // device layout: per matrix (k + 1) x W dwords (the last row zero), then
+    // the full rows at a 256-byte boundary
+    std::vector<uint32_t> dev_packed;
+    std::vector<size_t> dev_off;
+    for (uint32_t j = 0; j < c->nsets; ++j) {
+        dev_off.push_back(dev_packed.size());
+        const uint32_t W = c->W(j);
+        dev_packed.insert(dev_packed.end(), c->packed.begin() + c->packed_off[j],
+                          c->packed.begin() + c->packed_off[j] + (size_t)k * W);
+        dev_packed.insert(dev_packed.end(), W, 0u);
+    }
+    c->packed_off = dev_off;
+    c->packed = dev_packed;
+    size_t pbytes = (dev_packed.size() * sizeof(uint32_t) + 255) & ~(size_t)255;
+    c->dev_full_off = pbytes;
+    c->dev_bytes = pbytes + c->full_rows.size() * sizeof(bz::HostRow);
+    if (hipMalloc(&c->dev, c->dev_bytes) != hipSuccess) return fail(BZ_ENOMEM, "device allocation for Gamma_j");
+    hipError_t e1 = hipMemcpy(c->dev, dev_packed.data(), dev_packed.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy((char *)c->dev + pbytes, c->full_rows.data(),
+                              c->full_rows.size() * sizeof(bz::HostRow), hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipFree(c->dev);
+        return fail(BZ_EDEVICE, "upload of Gamma_j");
+    }
+    c->prepare_s = now_s() - t0;
+    *out = c.release();
+    return BZ_OK;
+}
+
+bz_status bz_code_get_info(const bz_code *c, bz_code_info *out, int32_t *set_of_column) {
+    if (!c || !out) return fail(BZ_EINVAL, "null argument");
+    out->n = c->n; out->k = c->k; out->num_full = c->num_full; out->partial_rank = c->partial_rank;
+    out->W_full = c->W_full; out->W_partial = c->W_partial;
+    if (set_of_column) std::memcpy(set_of_column, c->set_of_column.data(), c->n * sizeof(int32_t));
+    return BZ_OK;
+}
+
+bz_status bz_code_get_gamma(const bz_code *c, uint32_t matrix, uint64_t *rows, uint32_t ld_words) {
+    if (!c || !rows || matrix >= c->nsets || ld_words < (c->n + 63) / 64) return fail(BZ_EINVAL, "bad argument");
+    for (uint32_t i = 0; i < c->k; ++i)
+        for (uint32_t w = 0; w < ld_words; ++w)
+            rows[(size_t)i * ld_words + w] = w < (uint32_t)bz::kHostWords ? c->full_rows[(size_t)matrix * c->k + i][w] : 0;
+    return BZ_OK;
+}
+
+void bz_free(bz_code *c) {
+    if (!c) return;
+    if (c->dev) (void)hipFree(c->dev);
+    delete c;
+}
+
+bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opts *o, size_t *bytes) {
+    (void)o;
+    if (!bytes || (count && !codes)) return fail(BZ_EINVAL, "null argument");
+    *bytes = kWsBytes;
+    return BZ_OK;
+}
+
+bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
+    if (!c || !res) return fail(BZ_EINVAL, "null argument");
+    bz_opts opt{};
+    if (o) opt = *o;
+    res->d = 0; res->lower_bound = 0; res->upper_bound = 0; res->last_level = 0;
+    res->combinations = 0; res->stats_len = 0; res->launches = 0;
+    res->prepare_s = c->prepare_s; res->search_s = 0; res->kernel_s = 0;
+    if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
+    if (opt.slots_per_lane && opt.slots_per_lane != 2 && opt.slots_per_lane != 4 && opt.slots_per_lane != 8)
+        return fail(BZ_EINVAL, "slots_per_lane must be 0, 2, 4 or 8");
+    const bool stats = opt.flags & BZ_F_STATS, level_stop = opt.flags & BZ_F_LEVEL_STOP;
+    const bool want_witness = !(opt.flags & BZ_F_NO_WITNESS) && res->witness;
+    const uint32_t n = c->n, k = c->k, m_f = c->num_full, k_m = c->partial_rank;
+    const double t0 = now_s();
+
+    if (hipSetDevice(c->device) != hipSuccess) return fail(BZ_EDEVICE, "hipSetDevice");
+    if (opt.cancel) {
+        // the kernels read the cancel word: it must be host memory the device can map
+        hipPointerAttribute_t pa;
+        if (hipPointerGetAttributes(&pa, (const void *)opt.cancel) != hipSuccess ||
+            pa.type != hipMemoryTypeHost) {
+            (void)hipGetLastError();
+            return fail(BZ_EINVAL, "cancel must point to pinned host memory (hipHostMalloc)");
+        }
+    }
+    hipStream_t st = (hipStream_t)opt.hip_stream;
+    DeviceConst dc;
+    bz_status s0 = device_const(c->device, dc);
+    if (s0 != BZ_OK) return s0;
+
+    char *ws = (char *)opt.workspace;
+    bool own_ws = false;
+    if (ws) {
+        if (opt.workspace_bytes < kWsBytes) return fail(BZ_ENOMEM, "workspace smaller than bz_workspace_bytes");
+    } else {
+        if (hipMalloc((void **)&ws, kWsBytes) != hipSuccess) return fail(BZ_ENOMEM, "workspace allocation");
+        own_ws = true;
+    }
+    struct WsGuard {
+        char *p; bool own;
+        ~WsGuard() { if (own) (void)hipFree(p); }
+    } guard{ws, own_ws};
+
+    auto *d_key = (unsigned long long *)(ws + kWsTask);
+    auto *d_stats = d_key + 1;
+    auto *d_ncomb = d_key + 2;
+    auto *d_ctr = d_key + 3;
+    auto *d_rects = (bz::Rect *)(ws + kWsRects);
+
+    hipEvent_t ev0, ev1;
+    BZ_HIP(hipEventCreate(&ev0));
+    BZ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evg{ev0, ev1};
+
+    uint32_t U = n - k + 1, L = 1, Lcert = 1;
+    Best best;
+    bz_status status = BZ_OK;
+    if (k == n) {
+        // the loop of Alg. 1 never runs; any row of Gamma_1 has weight 1
+        res->d = 1; res->lower_bound = 1; res->upper_bound = 1;
+        if (want_witness)
+            for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = c->full_rows[0][w];
+        res->search_s = now_s() - t0;
+        return BZ_OK;
+    }
+
+    std::map<std::pair<uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots) -> plan
+    const uint64_t resident_waves = (uint64_t)dc.cus * 32;
+    bool done = false;
+    for (uint32_t g = 1; g <= k && L < U && !done; ++g) {
+        if (opt.max_level && g > opt.max_level) { status = BZ_ELIMIT; g_err = "max_level reached"; break; }
+        res->last_level = g;
+        for (uint32_t j = 0; j < c->nsets && !done; ++j) {
+            if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
+            const uint32_t W = c->W(j);
+            const uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : (stats ? 4u : default_slots(W));
+            auto key = std::make_pair(g, slots);
+            if (!plans.count(key)) {
+                std::string err;
+                bz::LevelPlan p;
+                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, 16 * resident_waves, p, err))
+                    return fail(BZ_ELIMIT, err);
+                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
+                plans[key] = std::move(p);
+            }
+            const bz::LevelPlan &plan = plans[key];
+            BZ_HIP(hipMemcpyAsync(d_rects, plan.rects.data(), plan.rects.size() * sizeof(bz::Rect),
+                                  hipMemcpyHostToDevice, st));
+            BZ_HIP(bz::launch_task_init(d_key, d_stats, d_ncomb, d_ctr, st));
+            bz::TaskArgs a{};
+            a.rows = (const uint32_t *)c->dev + c->packed_off[j];
+            a.binom = dc.binom;
+            a.rects = d_rects;
+            a.key = d_key; a.stats = d_stats; a.ncomb = d_ncomb; a.tile_ctr = d_ctr;
+            a.cancel = (const uint32_t *)opt.cancel;
+            a.nrects = (uint32_t)plan.rects.size();
+            a.k = k; a.k_low = c->k_low(j); a.g = g;
+            a.heads_per_tile = plan.heads_per_tile;
+            a.total_tiles = plan.total_tiles;
+            a.u_prev = U;
+            a.exit_at = stats ? 0u : Lcert;
+            const uint64_t blocks = (plan.total_tiles + 3) / 4;
+            const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
+            BZ_HIP(hipEventRecord(ev0, st));
+            BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
+            BZ_HIP(hipEventRecord(ev1, st));
+            unsigned long long words[3];
+            BZ_HIP(hipMemcpyAsync(words, d_key, sizeof(words), hipMemcpyDeviceToHost, st));
+            BZ_HIP(hipStreamSynchronize(st));
+            float ms = 0.f;
+            BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            res->kernel_s += ms * 1e-3;
+            res->launches++;
+            const uint32_t tmin = words[0] == ~0ull ? 0xffffffffu : (uint32_t)(words[0] >> bz::kTileBits);
+            const uint64_t ncomb = words[2];
+            const bool complete = ncomb == plan.combinations;
+            res->combinations += ncomb;
+            if (res->stats && res->stats_len < res->stats_cap) {
+                bz_level_stat &s = res->stats[res->stats_len];
+                s.matrix = (uint16_t)j; s.level = (uint16_t)g; s.min_weight = tmin;
+                s.count_at_min = stats ? (words[1] & ((1ull << 55) - 1)) : 0;
+                s.combinations = ncomb;
+            }
+            res->stats_len++;
+            if (tmin < U || (tmin == U && !best.have)) {
+                U = tmin;
+                best.have = true; best.j = j; best.g = g; best.tile = words[0] & bz::kTileMask;
+                best.slots = slots; best.ht = plan.heads_per_tile;
+                size_t lo = 0, hi = plan.rects.size() - 1;
+                while (lo < hi) {
+                    size_t mid = (lo + hi + 1) / 2;
+                    if (plan.rects[mid].tile_begin <= best.tile) lo = mid; else hi = mid - 1;
+                }
+                best.rect = plan.rects[lo];
+            }
+            if (opt.cancel && *opt.cancel && !complete) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
+            if (!complete) {
+                // a wave only leaves a task early once U <= the certified bound
+                if (U > Lcert) return fail(BZ_EDEVICE, "internal: task ended early without a certificate");
+                L = std::max(L, Lcert);
+                done = true;
+                break;
+            }
+            Lcert = std::max(Lcert, certified(j, g, m_f, k_m, k));
+            if (!level_stop) {
+                L = std::max(L, Lcert);
+                if (L >= U) done = true;
+            }
+        }
+        // Alg. 1's L once every matrix is done at level g
+        if (!done && status == BZ_OK) L = std::max(L, certified(k_m ? m_f : m_f - 1, g, m_f, k_m, k));
+    }
+    res->lower_bound = L;
+    res->upper_bound = U;
+    if (status == BZ_OK && res->stats && res->stats_len > res->stats_cap) {
+        status = BZ_ELIMIT;
+        g_err = "stats buffer too small";
+    }
+    if (status == BZ_OK && want_witness) {
+        if (!best.have) return fail(BZ_EDEVICE, "internal: no witness tile");
+        bz::RecoverArgs ra{};
+        const uint32_t j = best.j;
+        ra.rows = (const uint32_t *)c->dev + c->packed_off[j];
+        ra.full_rows = (const uint64_t *)((char *)c->dev + c->dev_full_off) + (size_t)j * k * bz::kHostWords;
+        ra.binom = dc.binom;
+        ra.rect = (const bz::Rect *)(ws + kWsRecoverRect);
+        ra.flag = (unsigned int *)(ws + kWsRecover);
+        ra.indices_len = (uint32_t *)(ws + kWsRecover + 4);
+        ra.codeword = (unsigned long long *)(ws + kWsRecover + 8);
+        ra.indices = (uint32_t *)(ws + kWsIndices);
+        ra.tile = best.tile; ra.slots = best.slots; ra.heads_per_tile = best.ht;
+        ra.W = c->W(j); ra.k_low = c->k_low(j); ra.target = U;
+        BZ_HIP(hipMemcpyAsync(ws + kWsRecoverRect, &best.rect, sizeof(bz::Rect), hipMemcpyHostToDevice, st));
+        BZ_HIP(hipMemsetAsync(ws + kWsRecover, 0, 64, st));
+        BZ_HIP(bz::launch_recover(ra, st));
+        unsigned long long back[5];
+        BZ_HIP(hipMemcpyAsync(back, ws + kWsRecover, sizeof(back), hipMemcpyDeviceToHost, st));
+        BZ_HIP(hipStreamSynchronize(st));
+        if ((uint32_t)back[0] != 1u) return fail(BZ_EDEVICE, "internal: witness not found in its tile");
+        for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = back[1 + w];
+    }
+    if (status == BZ_OK) res->d = U;
+    res->search_s = now_s() - t0;
+    return status;
+}
+
+bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
+                                bz_result *res, bz_status *per_code) {
+    if ((count && (!codes || !res || !per_code))) return fail(BZ_EINVAL, "null argument");
+    bz_status first = BZ_OK;
+    for (uint32_t i = 0; i < count; ++i) {
+        per_code[i] = bz_min_distance(codes[i], o, &res[i]);
+        if (per_code[i] != BZ_OK && first == BZ_OK) first = per_code[i];
+    }
+    return first;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- host-only inspection
+
+#include "../../include/bz_debug.h"
+
+extern "C" {
+
+bz_status bz_debug_prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_words,
+                                uint32_t *num_full, uint32_t *partial_rank, int32_t *set_of_column,
+                                uint64_t *gamma_rows, uint32_t gamma_cap_rows,
+                                uint32_t *packed, size_t packed_cap) {
+    bz_code c;
+    std::string err;
+    bz_status st = bz::prepare_host(G, k, n, ld_words, nullptr, c, err);
+    if (st != BZ_OK) return fail(st, err);
+    if (num_full) *num_full = c.num_full;
+    if (partial_rank) *partial_rank = c.partial_rank;
+    if (set_of_column) std::memcpy(set_of_column, c.set_of_column.data(), n * sizeof(int32_t));
+    if (gamma_rows) {
+        if ((uint64_t)c.nsets * k > gamma_cap_rows) return fail(BZ_ELIMIT, "gamma buffer too small");
+        for (size_t r = 0; r < c.full_rows.size(); ++r)
+            for (uint32_t w = 0; w < ld_words; ++w)
+                gamma_rows[r * ld_words + w] = w < (uint32_t)bz::kHostWords ? c.full_rows[r][w] : 0;
+    }
+    if (packed) {
+        if (c.packed.size() > packed_cap) return fail(BZ_ELIMIT, "packed buffer too small");
+        std::memcpy(packed, c.packed.data(), c.packed.size() * sizeof(uint32_t));
+    }
+    return BZ_OK;
+}
+
+bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
+                              uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
+                              uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used) {
+    if (k == 0 || k > (uint32_t)bz::kMaxN || (slots != 2 && slots != 4 && slots != 8))
+        return fail(BZ_EINVAL, "bad k or slots");
+    bz::LevelPlan p;
+    std::string err;
+    if (!bz::plan_level(k, g, slots, heads_per_tile, target_tiles, p, err)) return fail(BZ_ELIMIT, err);
+    if (nrects) *nrects = (uint32_t)p.rects.size();
+    if (total_tiles) *total_tiles = p.total_tiles;
+    if (heads_used) *heads_used = p.heads_per_tile;
+    if (rects) {
+        if (p.rects.size() > cap) return fail(BZ_ELIMIT, "rect buffer too small");
+        static_assert(sizeof(bz_debug_rect) == sizeof(bz::Rect), "layouts agree");
+        std::memcpy(rects, p.rects.data(), p.rects.size() * sizeof(bz::Rect));
+    }
+    return BZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host side of libbz and its HIP kernels.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bz.h"
+
+namespace bz {
+
+constexpr int kMaxN = BZ_MAX_N;
+constexpr int kHostWords = kMaxN / 64;   // 64-bit words of a host row
+constexpr int kMaxW = kMaxN / 32;        // 32-bit words of a device row
+constexpr int kBinomT = 64;              // columns 0..kBinomT of the device binomial table
+constexpr int kBinomRows = kMaxN + 1;    // rows 0..kMaxN
+constexpr uint64_t kBinomSat = ~0ull;    // stored for values >= 2^63
+constexpr int kMaxHeadSide = 64;         // the head side is a 64-bit mask
+constexpr int kWaveSize = 64;
+constexpr int kBlock = 256;              // threads per work-group (4 waves)
+
+using HostRow = std::array<uint64_t, kHostWords>;
+
+// One product of two colex subset spaces inside the g-subsets of [0, k):
+// every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a
+// head_t-subset of [head_off, head_off + head_n). The two ranges are disjoint.
+struct Rect {
+    uint32_t lane_off, lane_n, lane_t, head_off;
+    uint32_t head_n, head_t, _r0, _r1;
+    uint64_t lane_count, head_count;   // C(lane_n, lane_t), C(head_n, head_t)
+    uint64_t tile_begin;               // first tile index of this rectangle
+    uint64_t lane_blocks, head_blocks; // tiles along each factor
+    uint64_t _r2;
+};
+static_assert(sizeof(Rect) == 80, "Rect is 80 bytes");
+
+// Task key: minimum weight in the top 9 bits, tile index in the low 55.
+constexpr int kTileBits = 55;
+constexpr uint64_t kTileMask = (1ull << kTileBits) - 1;
+constexpr uint64_t kMaxTiles = 1ull << 40;
+
+// The tiling of one level g (shared by every Gamma_j of the code: all have k rows).
+struct LevelPlan {
+    uint32_t k = 0, g = 0, slots = 0, heads_per_tile = 0;
+    uint64_t total_tiles = 0, combinations = 0;
+    std::vector<Rect> rects;
+};
+
+bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
+                uint64_t target_tiles, LevelPlan &out, std::string &err);
+
+// C(a, b) with saturation at kBinomSat for values >= 2^63.
+uint64_t binom_sat(uint32_t a, uint32_t b);
+
+}  // namespace bz
+
+// A prepared code: Gamma_j on the host and on one device.
+struct bz_code {
+    uint32_t n = 0, k = 0, num_full = 0, partial_rank = 0;
+    uint32_t nsets = 0;                 // num_full + (partial_rank > 0)
+    uint32_t W_full = 0, W_partial = 0;
+    int device = 0;
+    std::vector<int32_t> set_of_column; // n entries
+    std::vector<bz::HostRow> full_rows; // nsets * k rows, original coordinates
+    std::vector<uint32_t> packed;       // per matrix: k * W(j) dwords, non-set columns
+    std::vector<size_t> packed_off;     // dword offset of matrix j in packed
+    void *dev = nullptr;                // device copy: packed rows, then full rows
+    size_t dev_bytes = 0;
+    size_t dev_full_off = 0;            // byte offset of the full rows in dev
+    double prepare_s = 0.0;
+    uint32_t W(uint32_t j) const { return j < num_full ? W_full : W_partial; }
+    uint32_t k_low(uint32_t j) const { return j < num_full ? k : partial_rank; }
+};
+
+namespace bz {
+bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
+                       const bz_prepare_opts *opts, bz_code &c, std::string &err);
+}

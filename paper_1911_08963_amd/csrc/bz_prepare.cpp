@@ -1,0 +1,160 @@
+// Host preparation of a code (Sec. 2.1 of arXiv:1911.08963): disjoint
+// information sets and the systematic matrices Gamma_j, then the bit-packed
+// device form of each Gamma_j.
+//
+// Information sets are found column by column: a column joins the current set
+// when it is independent of the columns already in it. Independence is
+// tested by reducing the column (a k-bit vector) against a GF(2) basis indexed
+// by leading bit. Scanning the available columns in ascending order gives the
+// greedy (first) basis. This is repeated on the remaining columns while they
+// still have rank k.
+//
+// Gamma_j is G brought to reduced echelon form with S_j's columns taken as
+// pivots first (in ascending order), then the other columns ascending. For a
+// full-rank S_j this puts I_k on S_j. For the leftover set it gives the block
+// form [[I_{k_m}, A], [0, B]] of Sec. 2.1. The reduced echelon form for a
+// given column order is unique, so Gamma_j is well defined.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+using ColVec = std::array<uint64_t, kHostWords>;   // a k-bit column, k <= 256
+
+inline bool bit(const HostRow &r, uint32_t c) { return (r[c >> 6] >> (c & 63)) & 1u; }
+
+int leading_bit(const ColVec &v) {
+    for (int w = kHostWords - 1; w >= 0; --w)
+        if (v[w]) return w * 64 + 63 - __builtin_clzll(v[w]);
+    return -1;
+}
+
+// A GF(2) basis of k-bit vectors, one slot per leading bit.
+struct XorBasis {
+    std::vector<ColVec> slot;
+    std::vector<char> used;
+    explicit XorBasis(uint32_t k) : slot(k), used(k, 0) {}
+    // Inserts v; returns true iff v was independent of the basis.
+    bool insert(ColVec v) {
+        for (;;) {
+            int lb = leading_bit(v);
+            if (lb < 0) return false;
+            if (!used[lb]) { slot[lb] = v; used[lb] = 1; return true; }
+            for (int w = 0; w < kHostWords; ++w) v[w] ^= slot[lb][w];
+        }
+    }
+};
+
+// Reduced echelon form of rows under a column order. Returns the rank.
+uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order) {
+    uint32_t k = (uint32_t)rows.size(), r = 0;
+    for (uint32_t c : order) {
+        if (r == k) break;
+        uint32_t p = r;
+        while (p < k && !bit(rows[p], c)) ++p;
+        if (p == k) continue;
+        std::swap(rows[p], rows[r]);
+        for (uint32_t i = 0; i < k; ++i) {
+            if (i == r || !bit(rows[i], c)) continue;
+            for (int w = 0; w < kHostWords; ++w) rows[i][w] ^= rows[r][w];
+        }
+        ++r;
+    }
+    return r;
+}
+
+}  // namespace
+
+uint64_t binom_sat(uint32_t a, uint32_t b) {
+    if (b > a) return 0;
+    if (b > a - b) b = a - b;
+    unsigned __int128 r = 1;
+    for (uint32_t i = 1; i <= b; ++i) {
+        r = r * (a - b + i) / i;
+        if (r >= ((unsigned __int128)1 << 63)) return kBinomSat;
+    }
+    return (uint64_t)r;
+}
+
+bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
+                       const bz_prepare_opts *opts, bz_code &c, std::string &err) {
+    if (!G) { err = "G is null"; return BZ_EINVAL; }
+    if (k == 0 || k > n || n > (uint32_t)kMaxN) { err = "need 0 < k <= n <= BZ_MAX_N"; return BZ_EINVAL; }
+    if (ld < (n + 63) / 64) { err = "ld_words < ceil(n/64)"; return BZ_EINVAL; }
+    if (opts && opts->perm_trials > 1) { err = "column-permutation search is not implemented"; return BZ_EINVAL; }
+
+    std::vector<HostRow> rows(k);
+    for (uint32_t i = 0; i < k; ++i) {
+        rows[i].fill(0);
+        for (uint32_t w = 0; w < (n + 63) / 64; ++w) rows[i][w] = G[(size_t)i * ld + w];
+        for (uint32_t cc = n; cc < (uint32_t)kMaxN; ++cc) rows[i][cc >> 6] &= ~(1ull << (cc & 63));
+    }
+    // columns as k-bit vectors
+    std::vector<ColVec> col(n);
+    for (uint32_t cc = 0; cc < n; ++cc) {
+        col[cc].fill(0);
+        for (uint32_t i = 0; i < k; ++i)
+            if (bit(rows[i], cc)) col[cc][i >> 6] |= 1ull << (i & 63);
+    }
+    std::vector<char> taken(n, 0);
+    std::vector<std::vector<uint32_t>> sets;
+    uint32_t num_full = 0, partial = 0;
+    for (;;) {
+        XorBasis basis(k);
+        std::vector<uint32_t> S;
+        for (uint32_t cc = 0; cc < n && S.size() < k; ++cc)
+            if (!taken[cc] && basis.insert(col[cc])) S.push_back(cc);
+        if (sets.empty() && S.size() < k) { err = "rank(G) < k"; return BZ_ERANK; }
+        if (S.size() == k) {
+            for (uint32_t cc : S) taken[cc] = 1;
+            sets.push_back(S);
+            ++num_full;
+            continue;
+        }
+        partial = (uint32_t)S.size();
+        if (partial) sets.push_back(S);
+        break;
+    }
+
+    c.n = n; c.k = k; c.num_full = num_full; c.partial_rank = partial;
+    c.nsets = (uint32_t)sets.size();
+    c.set_of_column.assign(n, -1);
+    c.W_full = (n - k + 31) / 32;
+    c.W_partial = partial ? (n - partial + 31) / 32 : 0;
+    c.full_rows.clear();
+    c.packed.clear();
+    c.packed_off.clear();
+    for (uint32_t j = 0; j < c.nsets; ++j) {
+        const std::vector<uint32_t> &S = sets[j];
+        std::vector<char> in(n, 0);
+        for (uint32_t cc : S) { in[cc] = 1; c.set_of_column[cc] = (int32_t)j; }
+        std::vector<uint32_t> order(S.begin(), S.end());
+        for (uint32_t cc = 0; cc < n; ++cc) if (!in[cc]) order.push_back(cc);
+        std::vector<HostRow> gam = rows;
+        uint32_t rk = reduce(gam, order);
+        if (rk != k) { err = "internal: Gamma_j lost rank"; return BZ_ERANK; }
+        // the identity part on S (rows 0..|S|-1) is implied by the pivot order
+        for (uint32_t i = 0; i < (uint32_t)S.size(); ++i)
+            if (!bit(gam[i], S[i])) { err = "internal: pivot order"; return BZ_ERANK; }
+        const uint32_t W = (j < num_full) ? c.W_full : c.W_partial;
+        c.packed_off.push_back(c.packed.size());
+        for (uint32_t i = 0; i < k; ++i) {
+            c.full_rows.push_back(gam[i]);
+            std::vector<uint32_t> words(W, 0);
+            uint32_t pos = 0;
+            for (uint32_t cc = 0; cc < n; ++cc) {
+                if (in[cc]) continue;
+                if (bit(gam[i], cc)) words[pos >> 5] |= 1u << (pos & 31);
+                ++pos;
+            }
+            c.packed.insert(c.packed.end(), words.begin(), words.end());
+        }
+    }
+    return BZ_OK;
+}
+
+}  // namespace bz
