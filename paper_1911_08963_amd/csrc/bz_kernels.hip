@@ -432,20 +432,24 @@ static hipError_t launch_one(const TaskArgs &a, uint32_t grid, size_t lds, hipSt
     return hipGetLastError();
 }
 
+template <int W, int SLOTS>
+static hipError_t launch_ws(const TaskArgs &a, bool partial, bool stats, uint32_t grid, size_t lds,
+                            hipStream_t st) {
+    if (stats) {
+        return partial ? launch_one<W, SLOTS, true, true>(a, grid, lds, st)
+                       : launch_one<W, SLOTS, false, true>(a, grid, lds, st);
+    }
+    return partial ? launch_one<W, SLOTS, true, false>(a, grid, lds, st)
+                   : launch_one<W, SLOTS, false, false>(a, grid, lds, st);
+}
+
 template <int W>
 static hipError_t launch_w(const TaskArgs &a, uint32_t slots, bool partial, bool stats, uint32_t grid,
                            size_t lds, hipStream_t st) {
-    if (stats) {
-        return partial ? launch_one<W, 4, true, true>(a, grid, lds, st)
-                       : launch_one<W, 4, false, true>(a, grid, lds, st);
-    }
     switch (slots) {
-    case 2: return partial ? launch_one<W, 2, true, false>(a, grid, lds, st)
-                           : launch_one<W, 2, false, false>(a, grid, lds, st);
-    case 4: return partial ? launch_one<W, 4, true, false>(a, grid, lds, st)
-                           : launch_one<W, 4, false, false>(a, grid, lds, st);
-    case 8: return partial ? launch_one<W, 8, true, false>(a, grid, lds, st)
-                           : launch_one<W, 8, false, false>(a, grid, lds, st);
+    case 2: return launch_ws<W, 2>(a, partial, stats, grid, lds, st);
+    case 4: return launch_ws<W, 4>(a, partial, stats, grid, lds, st);
+    case 8: return launch_ws<W, 8>(a, partial, stats, grid, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
