@@ -44,6 +44,10 @@ def main():
     ap.add_argument("--workload", default="plain192", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-max-level", type=int, default=6)
+    ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
+                    help="repeat the CPU-oracle sample until this much time has accumulated")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES three times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the search shards by "
@@ -61,6 +65,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_ref:
+        src = torch.empty(args.copy_ref, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": args.copy_ref, "launches": 3}), flush=True)
+        return
     c = inputs.plain_code(args.workload)
 
     def one_step():
@@ -127,12 +139,18 @@ def main():
     if not args.no_cpu:
         import oracle
         t = time.perf_counter()
-        ro = oracle.min_distance(c.G, c.n, max_level=args.cpu_max_level)
+        done = 0
+        reps = 0
+        while reps == 0 or time.perf_counter() - t < args.cpu_min_seconds:
+            ro = oracle.min_distance(c.G, c.n, max_level=args.cpu_max_level)
+            done += ro.combinations
+            reps += 1
         dt = time.perf_counter() - t
         line["cpu_baseline"] = {
-            "value": ro.combinations / dt, "unit": "combinations/s", "cores": 1, "kind": "oracle",
+            "value": done / dt, "unit": "combinations/s", "cores": 1, "kind": "oracle",
             "sample": f"single-threaded C oracle on the same code, levels 1-{args.cpu_max_level} of "
-                      f"all {ro.num_full} Gamma_j ({ro.combinations} combinations, {dt:.1f} s)",
+                      f"all {ro.num_full} Gamma_j, {reps} repetitions ({done} combinations in "
+                      f"{dt:.1f} s)",
         }
     print(json.dumps(line), flush=True)
 
