@@ -197,10 +197,11 @@ def workspace_bytes() -> int:
 
 
 def _workspace(device, nbytes):
+    """A cached torch device buffer of at least nbytes (grown on demand)."""
     import torch
-    key = (str(device), nbytes)
+    key = str(device)
     t = _ws_cache.get(key)
-    if t is None:
+    if t is None or t.numel() < nbytes:
         t = torch.empty(nbytes, dtype=torch.uint8, device=device)
         _ws_cache[key] = t
     return t
@@ -249,20 +250,22 @@ def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
     return out
 
 
-def min_distance_batch(codes, *, stats: bool = False, witness: bool = True, stream=None,
-                       stats_cap: int = 512, slots_per_lane: int = 0, heads_per_tile: int = 0):
+def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, witness: bool = True,
+                       max_level: int = 0, stream=None, stats_cap: int = 512, slots_per_lane: int = 0,
+                       heads_per_tile: int = 0, cancel=None):
     """bz_min_distance_batch: returns (list of SearchResult, list of status)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = stream if stream is not None else torch.cuda.current_stream(dev)
     cnt = len(codes)
     handles = (ctypes.c_void_p * cnt)(*[c.handle.value for c in codes])
-    flags = (BZ_F_STATS if stats else 0) | (0 if witness else BZ_F_NO_WITNESS)
+    flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
+        (0 if witness else BZ_F_NO_WITNESS)
     nbytes = ctypes.c_size_t()
-    o = _opts(flags, 0, stream.cuda_stream, None, None, slots_per_lane, heads_per_tile)
+    o = _opts(flags, max_level, stream.cuda_stream, None, cancel, slots_per_lane, heads_per_tile)
     _check(lib().bz_workspace_bytes(handles, cnt, ctypes.byref(o), ctypes.byref(nbytes)))
     ws = _workspace(dev, nbytes.value)
-    o = _opts(flags, 0, stream.cuda_stream, ws, None, slots_per_lane, heads_per_tile)
+    o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
     res = (Result * cnt)()
     wits = np.zeros((cnt, 4), dtype=np.uint64)
     stb = [(LevelStat * stats_cap)() for _ in range(cnt)]

@@ -87,6 +87,260 @@ struct Best {
     bz::Rect rect{};
 };
 
+
+// ---------------------------------------------------------------- batched search
+
+constexpr uint32_t kBatchSlots = 4;
+constexpr uint64_t kBatchMaxComb = 1ull << 50;   // levels with C(k, g) beyond this get no plan
+constexpr uint64_t kBatchTargetTiles = 64;        // tiles per task aimed at by the planner
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    std::vector<bz::BatchCode> codes;
+    std::vector<bz::CodeState> states;
+    std::vector<bz::PlanEntry> plans;
+    std::vector<bz::Rect> rects;
+    uint32_t done_init = 0, grid = 0, stats_total = 0;
+    size_t off_codes = 0, off_states = 0, off_plans = 0, off_rects = 0, off_stats = 0,
+           off_recover = 0, off_dummy = 0, off_done = 0, total = 0;
+};
+
+bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt, int cus, bool stats,
+                       BatchLayout &Lo) {
+    Lo = BatchLayout{};
+    std::map<uint32_t, std::pair<uint32_t, uint32_t>> plan_of_k;   // k -> (plan_base, g_max)
+    for (uint32_t i = 0; i < count; ++i) {
+        const bz_code *c = codes[i];
+        if (!c) return fail(BZ_EINVAL, "null code in batch");
+        if (plan_of_k.count(c->k)) continue;
+        const uint32_t base = (uint32_t)Lo.plans.size();
+        uint32_t gmax = 0;
+        for (uint32_t g = 1; g <= std::min<uint32_t>(c->k, bz::kBinomT); ++g) {
+            if (bz::binom_sat(c->k, g) >= kBatchMaxComb) break;
+            bz::LevelPlan p;
+            std::string err;
+            if (!bz::plan_level(c->k, g, kBatchSlots, opt.heads_per_tile, kBatchTargetTiles, p, err)) break;
+            bz::PlanEntry e{};
+            e.total_tiles = p.total_tiles;
+            e.rect_off = (uint32_t)Lo.rects.size();
+            e.nrects = (uint32_t)p.rects.size();
+            e.heads_per_tile = p.heads_per_tile;
+            Lo.rects.insert(Lo.rects.end(), p.rects.begin(), p.rects.end());
+            Lo.plans.push_back(e);
+            gmax = g;
+        }
+        plan_of_k[c->k] = {base, gmax};
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        const bz_code *c = codes[i];
+        bz::BatchCode d{};
+        d.rows = (const uint32_t *)c->dev;
+        d.full_rows = (const uint64_t *)((const char *)c->dev + c->dev_full_off);
+        d.n = c->n; d.k = c->k; d.m_f = c->num_full; d.k_m = c->partial_rank;
+        d.nsets = c->nsets; d.W_full = c->W_full; d.W_partial = c->W_partial;
+        d.plan_base = plan_of_k[c->k].first;
+        d.g_max = plan_of_k[c->k].second;
+        d.stats_off = Lo.stats_total;
+        d.stats_cap = c->nsets * std::max<uint32_t>(1, d.g_max);
+        Lo.stats_total += d.stats_cap;
+        Lo.codes.push_back(d);
+        bz::CodeState S{};
+        S.U = c->n - c->k + 1;
+        S.L = 1; S.Lcert = 1; S.last_level = 1;
+        if (c->k == c->n) {
+            S.cursor = (unsigned long long)(bz::kDoneEpoch << bz::kEpochShift);
+            S.L = 1; S.U = 1;
+            Lo.done_init++;
+        } else {
+            const bz::PlanEntry &P = Lo.plans[d.plan_base];
+            S.cursor = 0;
+            bz::TaskSlot &t = S.slot[0];
+            t.key = ~0ull; t.stats = ~0ull; t.ncomb = 0; t.completed = 0;
+            t.total_tiles = P.total_tiles;
+            t.j = 0; t.g = 1; t.rect_off = P.rect_off; t.nrects = P.nrects;
+            t.heads_per_tile = P.heads_per_tile;
+            t.exit_at = stats ? 0u : 1u;
+            t.u_prev = S.U;
+        }
+        Lo.states.push_back(S);
+    }
+    Lo.grid = (uint32_t)std::max(1, cus * bz::batch_blocks_per_cu(stats));
+    const size_t waves = (size_t)Lo.grid * (bz::kBlock / bz::kWaveSize);
+    size_t off = 0;
+    Lo.off_codes = off; off = align256(off + count * sizeof(bz::BatchCode));
+    Lo.off_states = off; off = align256(off + count * sizeof(bz::CodeState));
+    Lo.off_plans = off; off = align256(off + Lo.plans.size() * sizeof(bz::PlanEntry));
+    Lo.off_rects = off; off = align256(off + Lo.rects.size() * sizeof(bz::Rect));
+    Lo.off_stats = off; off = align256(off + (size_t)Lo.stats_total * sizeof(bz::BatchStat));
+    Lo.off_recover = off; off = align256(off + count * sizeof(bz::BatchRecover));
+    Lo.off_dummy = off; off = align256(off + waves * bz::kWaveSize * sizeof(unsigned long long));
+    Lo.off_done = off; off = align256(off + sizeof(uint32_t));
+    Lo.total = std::max(off, kWsBytes);
+    return BZ_OK;
+}
+
+bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_result *res,
+                    bz_status *per_code) {
+    if (count && (!codes || !res || !per_code)) return fail(BZ_EINVAL, "null argument");
+    if (count == 0) return BZ_OK;
+    bz_opts opt{};
+    if (o) opt = *o;
+    if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
+    if (opt.slots_per_lane && opt.slots_per_lane != kBatchSlots)
+        return fail(BZ_EINVAL, "the batched search uses 4 slots per lane");
+    const bool stats = opt.flags & BZ_F_STATS;
+    const double t0 = now_s();
+    for (uint32_t i = 0; i < count; ++i) {
+        per_code[i] = BZ_EDEVICE;
+        res[i].d = 0; res[i].lower_bound = 0; res[i].upper_bound = 0; res[i].last_level = 0;
+        res[i].combinations = 0; res[i].stats_len = 0; res[i].launches = 0;
+        res[i].search_s = 0; res[i].kernel_s = 0;
+        if (!codes[i]) return fail(BZ_EINVAL, "null code in batch");
+        res[i].prepare_s = codes[i]->prepare_s;
+        if (codes[i]->device != codes[0]->device) return fail(BZ_EINVAL, "codes of a batch must be on one device");
+    }
+    const int dev = codes[0]->device;
+    if (hipSetDevice(dev) != hipSuccess) return fail(BZ_EDEVICE, "hipSetDevice");
+    if (opt.cancel) {
+        hipPointerAttribute_t pa;
+        if (hipPointerGetAttributes(&pa, (const void *)opt.cancel) != hipSuccess || pa.type != hipMemoryTypeHost) {
+            (void)hipGetLastError();
+            return fail(BZ_EINVAL, "cancel must point to pinned host memory (hipHostMalloc)");
+        }
+    }
+    DeviceConst dc;
+    bz_status s0 = device_const(dev, dc);
+    if (s0 != BZ_OK) return s0;
+    BatchLayout Lo;
+    s0 = batch_layout(codes, count, opt, dc.cus, stats, Lo);
+    if (s0 != BZ_OK) return s0;
+
+    char *ws = (char *)opt.workspace;
+    bool own_ws = false;
+    if (ws) {
+        if (opt.workspace_bytes < Lo.total) return fail(BZ_ENOMEM, "workspace smaller than bz_workspace_bytes");
+    } else {
+        if (hipMalloc((void **)&ws, Lo.total) != hipSuccess) return fail(BZ_ENOMEM, "workspace allocation");
+        own_ws = true;
+    }
+    struct WsGuard {
+        char *p; bool own;
+        ~WsGuard() { if (own) (void)hipFree(p); }
+    } guard{ws, own_ws};
+
+    hipStream_t st = (hipStream_t)opt.hip_stream;
+    // uploads (not part of the captured graph)
+    const uint32_t done_init = Lo.done_init;
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_codes, Lo.codes.data(), count * sizeof(bz::BatchCode), hipMemcpyHostToDevice, st));
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_states, Lo.states.data(), count * sizeof(bz::CodeState), hipMemcpyHostToDevice, st));
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_plans, Lo.plans.data(), Lo.plans.size() * sizeof(bz::PlanEntry), hipMemcpyHostToDevice, st));
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_rects, Lo.rects.data(), Lo.rects.size() * sizeof(bz::Rect), hipMemcpyHostToDevice, st));
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_done, &done_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    BZ_HIP(hipMemsetAsync(ws + Lo.off_recover, 0, count * sizeof(bz::BatchRecover), st));
+
+    bz::BatchArgs b{};
+    b.codes = (const bz::BatchCode *)(ws + Lo.off_codes);
+    b.state = (bz::CodeState *)(ws + Lo.off_states);
+    b.plans = (const bz::PlanEntry *)(ws + Lo.off_plans);
+    b.rects = (const bz::Rect *)(ws + Lo.off_rects);
+    b.binom = dc.binom;
+    b.stats = (bz::BatchStat *)(ws + Lo.off_stats);
+    b.recover = (bz::BatchRecover *)(ws + Lo.off_recover);
+    b.dummy = (unsigned long long *)(ws + Lo.off_dummy);
+    b.done_count = (unsigned int *)(ws + Lo.off_done);
+    b.cancel = (const uint32_t *)opt.cancel;
+    b.ncodes = count; b.flags = opt.flags; b.max_level = opt.max_level; b.slots = kBatchSlots;
+
+    // one captured graph: the persistent search, then witness recovery
+    hipStream_t cs = nullptr;
+    hipEvent_t e_ready = nullptr, e_done = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipStream_t &cs; hipEvent_t &a, &b2, &c, &d; hipGraph_t &g; hipGraphExec_t &x;
+        ~GraphGuard() {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+            for (hipEvent_t e : {a, b2, c, d}) if (e) (void)hipEventDestroy(e);
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+    } gg{cs, e_ready, e_done, ev0, ev1, graph, exec};
+    BZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    BZ_HIP(hipEventCreate(&e_ready));
+    BZ_HIP(hipEventCreate(&e_done));
+    BZ_HIP(hipEventCreate(&ev0));
+    BZ_HIP(hipEventCreate(&ev1));
+    BZ_HIP(hipEventRecord(e_ready, st));
+    BZ_HIP(hipStreamWaitEvent(cs, e_ready, 0));
+    BZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t le = bz::launch_batch(b, Lo.grid, stats, cs);
+    hipError_t lr = (le == hipSuccess && !(opt.flags & BZ_F_NO_WITNESS)) ? bz::launch_batch_recover(b, cs) : hipSuccess;
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess || lr != hipSuccess || ec != hipSuccess)
+        return fail(BZ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : (lr != hipSuccess ? lr : ec)));
+    BZ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    BZ_HIP(hipEventRecord(ev0, cs));
+    BZ_HIP(hipGraphLaunch(exec, cs));
+    BZ_HIP(hipEventRecord(ev1, cs));
+    BZ_HIP(hipEventRecord(e_done, cs));
+    BZ_HIP(hipStreamWaitEvent(st, e_done, 0));
+
+    std::vector<bz::CodeState> states(count);
+    std::vector<bz::BatchStat> bstats(Lo.stats_total);
+    std::vector<bz::BatchRecover> rec(count);
+    BZ_HIP(hipMemcpyAsync(states.data(), ws + Lo.off_states, count * sizeof(bz::CodeState), hipMemcpyDeviceToHost, st));
+    if (Lo.stats_total)
+        BZ_HIP(hipMemcpyAsync(bstats.data(), ws + Lo.off_stats, Lo.stats_total * sizeof(bz::BatchStat), hipMemcpyDeviceToHost, st));
+    BZ_HIP(hipMemcpyAsync(rec.data(), ws + Lo.off_recover, count * sizeof(bz::BatchRecover), hipMemcpyDeviceToHost, st));
+    BZ_HIP(hipStreamSynchronize(st));
+    float ms = 0.f;
+    BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    const double wall = now_s() - t0;
+    const bool canceled = opt.cancel && *opt.cancel;
+    bz_status first = BZ_OK;
+    for (uint32_t i = 0; i < count; ++i) {
+        const bz::CodeState &S = states[i];
+        const bz_code *c = codes[i];
+        bz_result &r = res[i];
+        r.launches = 1;
+        r.kernel_s = ms * 1e-3;
+        r.search_s = wall;
+        r.lower_bound = S.L; r.upper_bound = S.U; r.last_level = c->k == c->n ? 0 : S.last_level;
+        r.combinations = S.combinations;
+        r.stats_len = S.nstats;
+        bz_status st_i = (bz_status)(int32_t)S.status;
+        const bool finished = (S.cursor >> bz::kEpochShift) == bz::kDoneEpoch;
+        if (!finished) st_i = canceled ? BZ_ECANCELED : BZ_EDEVICE;
+        if (r.stats) {
+            const uint32_t n = std::min(S.nstats, std::min(r.stats_cap, Lo.codes[i].stats_cap));
+            for (uint32_t t = 0; t < n; ++t) {
+                const bz::BatchStat &bs = bstats[Lo.codes[i].stats_off + t];
+                r.stats[t].matrix = bs.matrix; r.stats[t].level = bs.level;
+                r.stats[t].min_weight = bs.min_weight; r.stats[t].count_at_min = bs.count_at_min;
+                r.stats[t].combinations = bs.combinations;
+            }
+            if (st_i == BZ_OK && S.nstats > std::min(r.stats_cap, Lo.codes[i].stats_cap)) st_i = BZ_ELIMIT;
+        }
+        if (st_i == BZ_OK && !(opt.flags & BZ_F_NO_WITNESS) && r.witness) {
+            if (c->k == c->n) {
+                for (uint32_t w = 0; w < (c->n + 63) / 64; ++w) r.witness[w] = c->full_rows[0][w];
+            } else if (rec[i].flag == 1) {
+                for (uint32_t w = 0; w < (c->n + 63) / 64; ++w) r.witness[w] = rec[i].codeword[w];
+            } else {
+                st_i = BZ_EDEVICE;
+            }
+        }
+        if (st_i == BZ_OK) r.d = S.U;
+        per_code[i] = st_i;
+        if (st_i != BZ_OK && first == BZ_OK) {
+            first = st_i;
+            g_err = std::string("code ") + std::to_string(i) + ": " + bz_status_str(st_i);
+        }
+    }
+    return first;
+}
+
 }  // namespace
 
 extern "C" {
@@ -170,9 +424,20 @@ void bz_free(bz_code *c) {
 }
 
 bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opts *o, size_t *bytes) {
-    (void)o;
     if (!bytes || (count && !codes)) return fail(BZ_EINVAL, "null argument");
     *bytes = kWsBytes;
+    if (count == 0) return BZ_OK;
+    bz_opts opt{};
+    if (o) opt = *o;
+    if (!codes[0]) return fail(BZ_EINVAL, "null code");
+    if (hipSetDevice(codes[0]->device) != hipSuccess) return fail(BZ_EDEVICE, "hipSetDevice");
+    DeviceConst dc;
+    bz_status s0 = device_const(codes[0]->device, dc);
+    if (s0 != BZ_OK) return s0;
+    BatchLayout Lo;
+    s0 = batch_layout(codes, count, opt, dc.cus, (opt.flags & BZ_F_STATS) != 0, Lo);
+    if (s0 != BZ_OK) return s0;
+    *bytes = Lo.total;
     return BZ_OK;
 }
 
@@ -367,13 +632,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
 
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
                                 bz_result *res, bz_status *per_code) {
-    if ((count && (!codes || !res || !per_code))) return fail(BZ_EINVAL, "null argument");
-    bz_status first = BZ_OK;
-    for (uint32_t i = 0; i < count; ++i) {
-        per_code[i] = bz_min_distance(codes[i], o, &res[i]);
-        if (per_code[i] != BZ_OK && first == BZ_OK) first = per_code[i];
-    }
-    return first;
+    return batch_run(codes, count, o, res, per_code);
 }
 
 }  // extern "C"

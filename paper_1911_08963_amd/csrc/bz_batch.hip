@@ -1,0 +1,364 @@
+// Batched persistent search behind bz_min_distance_batch: one launch drains
+// the Brouwer-Zimmermann level loop (Alg. 1 of arXiv:1911.08963) of many
+// codes at once.
+//
+// Every code has one current task, (Gamma_j, g), at a time. Its tiles are
+// handed out by a cursor word (epoch << 40 | next tile); a wave claims one tile
+// with a CAS on that word, runs the same tile code as the single-code kernel
+// (bz_tile.h) and then counts the tile as finished. The wave that finishes a
+// task's last tile advances the code on the device: it records the task's
+// statistics, moves U, applies the certified lower bound, and either
+// publishes the next task (the other of the code's two task slots, then a
+// release store of the new epoch) or marks the code finished. This is the
+// coordinator/worker scheme of the paper's dynamic algorithms (Sec. 3.2)
+// collapsed into one GPU: the coordinator is whichever wave finishes last.
+// Waves leave when every code is finished or the cancel word is set.
+//
+// Atomics whose result the wave needs are issued by all 64 lanes: lane 0 on
+// the real word, the other lanes on per-wave scratch words. The wave then
+// reads lane 0's result with readfirstlane, with no lane-dependent branch
+// around it.
+#include <hip/hip_runtime.h>
+
+#include "bz_internal.h"
+#include "bz_kernels.h"
+#include "bz_tile.h"
+
+namespace bz {
+
+__device__ __forceinline__ bool wave_cas64(unsigned long long *p, unsigned long long expect,
+                                           unsigned long long desired, unsigned long long *dummy,
+                                           uint32_t lane) {
+    unsigned long long *addr = lane == 0 ? p : dummy + lane;
+    unsigned long long e = expect;
+    bool ok = __hip_atomic_compare_exchange_strong(addr, &e, desired, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return uni(ok ? 1u : 0u) != 0u;
+}
+
+__device__ __forceinline__ unsigned long long wave_fetch_add64(unsigned long long *p, unsigned long long v,
+                                                               unsigned long long *dummy, uint32_t lane) {
+    unsigned long long *addr = lane == 0 ? p : dummy + lane;
+    unsigned long long old = __hip_atomic_fetch_add(addr, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return uni64(old);
+}
+
+// Lower bound certified once Gamma_0..Gamma_j are done at level g and the
+// later matrices at level g - 1 (j == m_f is the partial matrix).
+__device__ __forceinline__ uint32_t certified_bound(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m,
+                                                    uint32_t k) {
+    if (j >= m_f) {
+        int e = k_m ? (int)g + 1 - (int)k + (int)k_m : 0;
+        return m_f * (g + 1) + (uint32_t)(e > 0 ? e : 0);
+    }
+    int e = k_m ? (int)g - (int)k + (int)k_m : 0;
+    return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)(e > 0 ? e : 0);
+}
+
+template <int SLOTS, bool STATS>
+__device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, uint64_t epoch, uint64_t tile,
+                                           uint32_t lane, cptr64 binom_c) {
+    const BatchCode &D = b.codes[code];
+    TaskSlot *s = &b.state[code].slot[epoch & 1];
+    const uint32_t j = uni(s->j), g = uni(s->g);
+    const uint32_t k = uni(D.k), m_f = uni(D.m_f);
+    const bool partial = j >= m_f;
+    const uint32_t W = uni(partial ? D.W_partial : D.W_full);
+    const uint32_t W_full = uni(D.W_full);
+    const uint32_t *rows = D.rows + (size_t)(partial ? m_f : j) * (k + 1) * W_full;
+    TaskArgs a{};
+    a.rows = rows;
+    a.binom = b.binom;
+    a.rects = b.rects + uni(s->rect_off);
+    a.key = &s->key;
+    a.stats = &s->stats;
+    a.ncomb = &s->ncomb;
+    a.nrects = uni(s->nrects);
+    a.k = k;
+    a.k_low = partial ? uni(D.k_m) : k;
+    a.g = g;
+    a.heads_per_tile = uni(s->heads_per_tile);
+    a.total_tiles = uni64(s->total_tiles);
+    a.u_prev = uni(s->u_prev);
+    a.exit_at = uni(s->exit_at);
+    if (a.exit_at) {
+        unsigned long long kv = __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t cur = min((uint32_t)(kv >> kTileBits), a.u_prev);
+        if (uni(cur) <= a.exit_at) return;        // the bound is met: skip, still counted as done
+    }
+    cptr32 rc = (cptr32)rows;
+    cptr_rect rp = (cptr_rect)a.rects;
+    const uint64_t *gb = b.binom;
+    constexpr uint32_t BT = kBinomT + 1;
+    switch (W * 2 + (partial ? 1u : 0u)) {
+#define BZ_CASE(WW)                                                                                   \
+    case WW * 2: run_tile<WW, SLOTS, false, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane); break; \
+    case WW * 2 + 1: run_tile<WW, SLOTS, true, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane); break;
+        BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
+#undef BZ_CASE
+    default: break;
+    }
+}
+
+// The last wave of a task: bookkeeping of Alg. 1 for one code, then the next
+// task or the end. All values are uniform; lane 0 does the stores.
+template <bool STATS>
+__device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch, uint32_t lane) {
+    CodeState *S = &b.state[code];
+    const BatchCode &D = b.codes[code];
+    TaskSlot *s = &S->slot[epoch & 1];
+    const uint32_t j = uni(s->j), g = uni(s->g);
+    const uint32_t k = uni(D.k), m_f = uni(D.m_f), k_m = uni(D.k_m), nsets = uni(D.nsets);
+    const unsigned long long key = uni64(__hip_atomic_load(&s->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long sw = uni64(__hip_atomic_load(&s->stats, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long nc = uni64(__hip_atomic_load(&s->ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
+    const uint64_t total = uni64(b.binom[(size_t)k * (kBinomT + 1) + g]);
+    const bool complete = nc == total;
+
+    uint32_t U = uni(S->U), L = uni(S->L), Lcert = uni(S->Lcert), nstats = uni(S->nstats);
+    uint32_t have_best = uni(S->have_best), best_j = uni(S->best_j), best_g = uni(S->best_g);
+    uint64_t best_tile = uni64(S->best_tile), combos = uni64(S->combinations) + nc;
+    uint32_t last_level = uni(S->last_level), status = uni(S->status);
+    if (lane == 0 && nstats < D.stats_cap) {
+        BatchStat st;
+        st.matrix = (uint16_t)j;
+        st.level = (uint16_t)g;
+        st.min_weight = tmin;
+        st.count_at_min = STATS ? (sw & ((1ull << kTileBits) - 1)) : 0ull;
+        st.combinations = nc;
+        b.stats[D.stats_off + nstats] = st;
+    }
+    nstats++;
+    if (tmin < U || (tmin == U && !have_best)) {
+        U = tmin;
+        have_best = 1; best_j = j; best_g = g; best_tile = key & kTileMask;
+    }
+    bool done = false;
+    uint32_t nj = 0, ng = 0;
+    if (!complete) {
+        // a wave skips tiles only once U <= the bound certified before this task
+        L = max(L, Lcert);
+        done = true;
+    } else {
+        const uint32_t Lc = certified_bound(j, g, m_f, k_m, k);
+        Lcert = max(Lcert, Lc);
+        // per-Gamma stop: check after every matrix; Alg. 1 as printed: only once a level is done
+        const bool check = !(b.flags & BZ_F_LEVEL_STOP) || j + 1 == nsets;
+        if (check) L = max(L, Lc);
+        if (check && L >= U) {
+            done = true;
+        } else {
+            nj = j + 1; ng = g;
+            if (nj == nsets) { nj = 0; ng = g + 1; }
+            if (ng > k) {
+                done = true;                                  // everything enumerated: d = U
+            } else if (ng > uni(D.g_max) || (b.max_level && ng > b.max_level)) {
+                done = true;
+                status = (uint32_t)(int32_t)BZ_ELIMIT;
+            }
+        }
+    }
+    if (!done && ng > last_level) last_level = ng;
+    if (lane == 0) {
+        S->U = U; S->L = L; S->Lcert = Lcert; S->nstats = nstats;
+        S->have_best = have_best; S->best_j = best_j; S->best_g = best_g; S->best_tile = best_tile;
+        S->combinations = combos; S->last_level = last_level; S->status = status;
+        if (!done) {
+            const PlanEntry P = b.plans[D.plan_base + ng - 1];
+            TaskSlot *n = &S->slot[(epoch + 1) & 1];
+            n->key = ~0ull;
+            n->stats = ~0ull;
+            n->ncomb = 0;
+            n->completed = 0;
+            n->total_tiles = P.total_tiles;
+            n->j = nj; n->g = ng;
+            n->rect_off = P.rect_off; n->nrects = P.nrects; n->heads_per_tile = P.heads_per_tile;
+            n->exit_at = STATS ? 0u : Lcert;
+            n->u_prev = U;
+            __hip_atomic_store(&S->cursor, (unsigned long long)((epoch + 1) << kEpochShift), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&S->cursor, (unsigned long long)(kDoneEpoch << kEpochShift), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int SLOTS, bool STATS>
+__global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
+    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
+    const uint32_t wave = blockIdx.x * (blockDim.x / kWaveSize) + uni(threadIdx.x / kWaveSize);
+    unsigned long long *dummy = b.dummy + (size_t)wave * kWaveSize;
+    cptr64 binom_c = (cptr64)b.binom;
+    uint32_t c = wave % b.ncodes;
+    for (;;) {
+        const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if (dc >= b.ncodes) break;
+        if (b.cancel) {
+            uint32_t cv = __hip_atomic_load(b.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (uni(cv)) break;
+        }
+        // find a code with a tile to hand out, starting from the last one served
+        bool got = false;
+        uint32_t code = 0;
+        uint64_t epoch = 0, tile = 0;
+        for (uint32_t p = 0; p < b.ncodes && !got; ++p) {
+            uint32_t cc = c + p;
+            if (cc >= b.ncodes) cc -= b.ncodes;
+            CodeState *S = b.state + cc;
+            const unsigned long long w =
+                uni64(__hip_atomic_load(&S->cursor, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            const uint64_t e = w >> kEpochShift;
+            if (e == kDoneEpoch) continue;
+            const uint64_t t = w & kCursorMask;
+            const uint64_t T = uni64(__hip_atomic_load(&S->slot[e & 1].total_tiles, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+            if (t >= T) continue;
+            if (wave_cas64(&S->cursor, w, w + 1, dummy, lane)) {
+                got = true; code = cc; epoch = e; tile = t;
+            }
+        }
+        if (!got) {
+            __builtin_amdgcn_s_sleep(16);
+            continue;
+        }
+        c = code;
+        batch_tile<SLOTS, STATS>(b, code, epoch, tile, lane, binom_c);
+        TaskSlot *s = &b.state[code].slot[epoch & 1];
+        const uint64_t T = uni64(s->total_tiles);
+        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, dummy, lane);
+        if (prev + 1 == T) batch_advance<STATS>(b, code, epoch, lane);
+    }
+}
+
+// Witness of each finished code: one work-group per code re-scans the winning
+// tile. Its lane subsets' sums go to LDS first; then every thread takes head
+// steps, builds the head sum from scratch, and compares every lane sum
+// against the target weight. The first match writes the row indices and the
+// codeword (XOR of the full rows).
+constexpr int kRecoverLanes = kWaveSize * 8;
+
+__device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, uint32_t off, uint32_t nside,
+                                uint32_t *idx) {
+    uint32_t hi = nside - 1;
+    for (uint32_t i = t; i >= 1; --i) {
+        uint32_t lo = i - 1, c = hi;
+        while (lo < c) {
+            uint32_t mid = (lo + c + 1) >> 1;
+            if (binom[mid * (kBinomT + 1) + i] <= r) lo = mid; else c = mid - 1;
+        }
+        r -= binom[lo * (kBinomT + 1) + i];
+        idx[t - i] = off + lo;
+        hi = lo - 1;
+    }
+    return t;
+}
+
+__global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
+    __shared__ uint32_t sP[kRecoverLanes * kMaxW];
+    __shared__ uint32_t sLow[kRecoverLanes];
+    __shared__ uint32_t sFound;
+    const uint32_t code = blockIdx.x;
+    const CodeState *S = b.state + code;
+    const BatchCode &D = b.codes[code];
+    BatchRecover *out = b.recover + code;
+    if (S->status != 0 || !S->have_best || D.k == D.n) return;   // uniform per block
+    const uint32_t j = S->best_j, g = S->best_g, k = D.k;
+    (void)g;
+    const bool partial = j >= D.m_f;
+    const uint32_t W = partial ? D.W_partial : D.W_full;
+    const uint32_t k_low = partial ? D.k_m : k;
+    const uint32_t *rows = D.rows + (size_t)(partial ? D.m_f : j) * (k + 1) * D.W_full;
+    const uint64_t *full = D.full_rows + (size_t)j * k * kHostWords;
+    const PlanEntry P = b.plans[D.plan_base + g - 1];
+    const Rect *rects = b.rects + P.rect_off;
+    const uint64_t tile = S->best_tile;
+    uint32_t lo = 0, hi = P.nrects - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (rects[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    const Rect R = rects[lo];
+    const uint64_t local = tile - R.tile_begin;
+    const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
+    const uint32_t lane_items = kWaveSize * b.slots;
+    const uint64_t q0 = lb * lane_items;
+    const uint32_t nl = (uint32_t)((R.lane_count - q0) < lane_items ? (R.lane_count - q0) : lane_items);
+    const uint64_t h0 = hb * P.heads_per_tile;
+    const uint32_t nh = (uint32_t)((R.head_count - h0) < P.heads_per_tile ? (R.head_count - h0) : P.heads_per_tile);
+    uint32_t idx[kBinomT];
+    for (uint32_t q = threadIdx.x; q < nl; q += blockDim.x) {
+        unrank_into(b.binom, q0 + q, R.lane_t, R.lane_off, R.lane_n, idx);
+        uint32_t low = 0;
+        for (uint32_t w = 0; w < W; ++w) sP[q * kMaxW + w] = 0;
+        for (uint32_t i = 0; i < R.lane_t; ++i) {
+            for (uint32_t w = 0; w < W; ++w) sP[q * kMaxW + w] ^= rows[idx[i] * W + w];
+            low += idx[i] < k_low ? 1u : 0u;
+        }
+        sLow[q] = low;
+    }
+    if (threadIdx.x == 0) sFound = 0;
+    __syncthreads();
+    const uint32_t target = S->U;
+    for (uint32_t h = threadIdx.x; h < nh; h += blockDim.x) {
+        if (__hip_atomic_load(&sFound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+        uint32_t H[kMaxW];
+        for (uint32_t w = 0; w < kMaxW; ++w) H[w] = 0;
+        uint32_t hl = 0;
+        if (R.head_t) {
+            unrank_into(b.binom, h0 + h, R.head_t, R.head_off, R.head_n, idx);
+            for (uint32_t i = 0; i < R.head_t; ++i) {
+                for (uint32_t w = 0; w < W; ++w) H[w] ^= rows[idx[i] * W + w];
+                hl += idx[i] < k_low ? 1u : 0u;
+            }
+        }
+        for (uint32_t q = 0; q < nl; ++q) {
+            // identity part: rows below k_low (every row of a full-rank Gamma_j)
+            uint32_t wt = sLow[q] + hl;
+            for (uint32_t w = 0; w < W; ++w) wt += __builtin_popcount(sP[q * kMaxW + w] ^ H[w]);
+            if (wt != target) continue;
+            if (atomicCAS(&sFound, 0u, 1u) != 0u) break;
+            // rebuild the combination's row indices and the codeword
+            uint32_t n_idx = 0;
+            uint32_t all[kBinomT];
+            n_idx += unrank_into(b.binom, q0 + q, R.lane_t, R.lane_off, R.lane_n, all);
+            if (R.head_t) n_idx += unrank_into(b.binom, h0 + h, R.head_t, R.head_off, R.head_n, all + n_idx);
+            uint64_t cw[kHostWords];
+            for (int w = 0; w < kHostWords; ++w) cw[w] = 0;
+            for (uint32_t i = 0; i < n_idx; ++i)
+                for (int w = 0; w < kHostWords; ++w) cw[w] ^= full[(size_t)all[i] * kHostWords + w];
+            for (int w = 0; w < kHostWords; ++w) out->codeword[w] = cw[w];
+            for (uint32_t i = 0; i < n_idx; ++i) out->indices[i] = all[i];
+            out->len = n_idx;
+            __hip_atomic_store(&out->flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+}
+
+template <int SLOTS, bool STATS>
+static hipError_t launch_batch_t(const BatchArgs &b, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL((bz_batch_kernel<SLOTS, STATS>), dim3(grid), dim3(kBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st) {
+    if (b.slots != 4) return hipErrorInvalidValue;
+    return stats ? launch_batch_t<4, true>(b, grid, st) : launch_batch_t<4, false>(b, grid, st);
+}
+
+int batch_blocks_per_cu(bool stats) {
+    int n = 0;
+    hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<4, true>, kBlock, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<4, false>, kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_batch_recover(const BatchArgs &b, hipStream_t st) {
+    hipLaunchKernelGGL(bz_batch_recover_kernel, dim3(b.ncodes), dim3(kBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -37,6 +37,79 @@ struct RecoverArgs {
     uint32_t slots, heads_per_tile, W, k_low, target;
 };
 
+// ---- batched persistent search (bz_min_distance_batch)
+
+// Tiling of level g for one k: rects[rect_off .. rect_off + nrects).
+struct PlanEntry {
+    uint64_t total_tiles;
+    uint32_t rect_off, nrects, heads_per_tile, _pad[3];
+};
+static_assert(sizeof(PlanEntry) == 32, "PlanEntry is 32 bytes");
+
+// Immutable description of one code of a batch.
+struct BatchCode {
+    const uint32_t *rows;        // packed rows: Gamma_j at j * (k + 1) * W_full, Gamma_m after them
+    const uint64_t *full_rows;   // Gamma_j full rows at j * k * kHostWords
+    uint32_t n, k, m_f, k_m;
+    uint32_t nsets, W_full, W_partial, g_max;   // plans exist for levels 1..g_max
+    uint32_t plan_base;          // plan of level g is plans[plan_base + g - 1]
+    uint32_t stats_off, stats_cap, _pad;
+};
+
+// One task of one code; two per code, selected by the parity of the epoch.
+struct alignas(64) TaskSlot {
+    unsigned long long key;       // (min weight << 55) | tile
+    unsigned long long stats;     // (min << 55) | count
+    unsigned long long ncomb;     // combinations enumerated
+    unsigned long long completed; // tiles finished
+    uint64_t total_tiles;
+    uint32_t j, g, rect_off, nrects, heads_per_tile, exit_at;
+    uint32_t u_prev, _pad[3];
+};
+
+constexpr uint64_t kEpochShift = 40;
+constexpr uint64_t kCursorMask = (1ull << kEpochShift) - 1;
+constexpr uint64_t kDoneEpoch = (1ull << 24) - 1;
+
+struct alignas(64) CodeState {
+    unsigned long long cursor;    // (epoch << 40) | next tile to hand out; epoch kDoneEpoch = finished
+    uint32_t U, L, Lcert, status;
+    uint32_t last_level, nstats, have_best, best_j;
+    uint32_t best_g, _pad0;
+    uint64_t best_tile, combinations;
+    TaskSlot slot[2];
+};
+
+struct BatchStat {                // one completed task
+    uint16_t matrix, level;
+    uint32_t min_weight;
+    uint64_t count_at_min, combinations;
+};
+
+struct BatchRecover {             // witness of one code
+    uint32_t flag, len, _pad[2];
+    uint64_t codeword[kHostWords];
+    uint32_t indices[kBinomT];
+};
+
+struct BatchArgs {
+    const BatchCode *codes;
+    CodeState *state;
+    const PlanEntry *plans;
+    const Rect *rects;
+    const uint64_t *binom;
+    BatchStat *stats;
+    BatchRecover *recover;
+    unsigned long long *dummy;    // 64 words per wave: targets of the lanes other than lane 0
+    unsigned int *done_count;
+    const uint32_t *cancel;
+    uint32_t ncodes, flags, max_level, slots;
+};
+
+hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st);
+hipError_t launch_batch_recover(const BatchArgs &b, hipStream_t st);
+int batch_blocks_per_cu(bool stats);
+
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st);
 size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W);

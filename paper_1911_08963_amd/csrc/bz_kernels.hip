@@ -1,327 +1,21 @@
-// HIP kernels for gfx950: enumeration of row sums of one Gamma matrix at one
-// level (the inner loop of Alg. 1 of arXiv:1911.08963), and witness recovery.
+// HIP kernels for gfx950 behind bz_min_distance: the enumeration of row sums
+// of one Gamma matrix at one level (the inner loop of Alg. 1 of
+// arXiv:1911.08963), the task reset, and witness recovery. The tile itself
+// (decomposition, registers, instruction mix) is described in bz_tile.h.
 //
-// Work decomposition (see bz_plan.cpp): a level of Gamma_j is a list of
-// rectangles, each the product of a lane factor (lane_t-subsets of one row
-// range) and a head factor (head_t-subsets of another, at most 64 rows). A
-// wave tile is 64 * SLOTS lane subsets by up to heads_per_tile consecutive
-// head subsets in colex order.
-//  - Lanes: each lane unranks its SLOTS lane subsets (combinatorial number
-//    system, binomials in LDS) and keeps their XOR sums P[s] in VGPRs.
-//  - Head: the whole wave steps the head subset as a 64-bit mask in SGPRs. The
-//    smallest element runs fastest: H = S2 ^ row[e], where S2 is the XOR of
-//    the other head rows. S2 changes only when the smallest element wraps
-//    (a Gosper step on the mask). Rows come through scalar loads.
-//  - Per combination, per 32-bit word: one v_xor (SGPR ^ VGPR) and one
-//    v_bcnt (popcount plus accumulate). One v_min3 folds two combinations
-//    into the running minimum. That is 2W + 1/2 VALU operations per
-//    combination. The identity part of a full-rank Gamma_j weighs exactly g,
-//    which is added once per tile.
-//  - The partial Gamma_m weighs |c & [0, k_m)| on its identity part. The head's
-//    share enters through the bcnt accumulator (an SGPR operand). The lane's
-//    share is added per slot when the tile ends.
-//  - End of a tile: a wave-wide minimum, then one 64-bit atomicMin of
-//    (weight << 32 | tile) into the task's key. In statistics mode also the
-//    number of combinations reaching the tile minimum, merged by a CAS loop.
-//  - Waves take tiles from an atomic counter. Before each tile a wave reads
-//    the task key and stops when the upper bound has reached the certified
-//    lower bound (fast mode only) or when the caller's cancel word is set.
+// bz_enum_kernel stages the Gamma_j rows and the binomials C(x, y), x <= k,
+// y <= g, in LDS once per work-group, then deals tiles round-robin to its waves
+// by uniform arithmetic (tiles of a level cost the same, so no work queue is
+// needed inside one task). Before each tile a wave reads the task key and
+// stops when the upper bound has reached the certified lower bound (fast mode
+// only) or when the caller's cancel word is set.
 #include <hip/hip_runtime.h>
 
 #include "bz_internal.h"
 #include "bz_kernels.h"
+#include "bz_tile.h"
 
 namespace bz {
-
-typedef const __attribute__((address_space(4))) uint32_t *cptr32;
-typedef const __attribute__((address_space(4))) uint64_t *cptr64;
-typedef const __attribute__((address_space(4))) Rect *cptr_rect;
-
-__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
-    return v;
-}
-
-// Popcount-accumulate and three-way minimum as single VALU instructions.
-// Written as ALU-only inline assembly so that the compiler keeps the
-// accumulate chain (it would otherwise split it into separate counts joined
-// by v_add3, and fold pairwise minima into a deeper tree).
-__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
-    uint32_t r;
-    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
-    return r;
-}
-__device__ __forceinline__ uint32_t bcnt_acc_s(uint32_t x, uint32_t acc_uniform) {
-    uint32_t r;
-    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "s"(acc_uniform));
-    return r;
-}
-__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
-// Statistics word: minimum in the top 9 bits, count in the low 55.
-constexpr int kCountBits = 55;
-constexpr unsigned long long kCountMask = (1ull << kCountBits) - 1;
-
-__device__ void stats_merge(unsigned long long *p, uint32_t w, uint64_t cnt) {
-    unsigned long long mine = ((unsigned long long)w << kCountBits) | (cnt & kCountMask);
-    unsigned long long old = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        uint32_t ow = (uint32_t)(old >> kCountBits);
-        unsigned long long nv;
-        if (w < ow) nv = mine;
-        else if (w > ow) return;
-        else nv = old + (cnt & kCountMask);
-        if (__hip_atomic_compare_exchange_strong(p, &old, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return;
-    }
-}
-
-// Largest c in [lo, hi] with C(c, i) <= r; binomials from LDS (row stride bt).
-__device__ __forceinline__ uint32_t colex_digit(const uint64_t *sb, uint32_t bt, uint32_t i,
-                                                 uint32_t lo, uint32_t hi, uint64_t r) {
-    while (lo < hi) {
-        uint32_t mid = (lo + hi + 1) >> 1;
-        if (sb[mid * bt + i] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// The same for uniform values, with binomials through the scalar cache.
-__device__ __forceinline__ uint32_t colex_digit_s(cptr64 gb, uint32_t i, uint32_t lo, uint32_t hi,
-                                                   uint64_t r) {
-    while (lo < hi) {
-        uint32_t mid = (lo + hi + 1) >> 1;
-        if (gb[mid * (kBinomT + 1) + i] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int W, int SLOTS, bool PARTIAL, bool STATS>
-__device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
-                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
-                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
-    // ---- locate the rectangle (uniform binary search on tile_begin)
-    uint32_t ri = 0;
-    {
-        uint32_t lo = 0, hi = a.nrects - 1;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (rect_p[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-        }
-        ri = uni(lo);
-    }
-    const uint32_t lane_off = rect_p[ri].lane_off, lane_n = rect_p[ri].lane_n,
-                   lane_t = rect_p[ri].lane_t, head_off = rect_p[ri].head_off,
-                   head_n = rect_p[ri].head_n, head_t = rect_p[ri].head_t;
-    const uint64_t lane_count = rect_p[ri].lane_count, head_count = rect_p[ri].head_count,
-                   head_blocks = rect_p[ri].head_blocks;
-    const uint64_t local = tile - rect_p[ri].tile_begin;
-    const uint64_t lb = local / head_blocks, hb = local - lb * head_blocks;
-
-    // ---- lane subsets: XOR sums and identity weight
-    uint32_t P[SLOTS][W];
-    uint32_t low[SLOTS];
-    uint32_t pen[SLOTS];
-    uint32_t nvalid = 0;
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const uint64_t q = (uint64_t)lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize + lane;
-        const bool valid = q < lane_count;
-#pragma unroll
-        for (int w = 0; w < W; ++w) P[s][w] = 0;
-        low[s] = 0;
-        pen[s] = valid ? 0u : 0x10000u;
-        if (valid) {
-            uint64_t r = q;
-            uint32_t hi = lane_n - 1;
-            for (uint32_t i = lane_t; i >= 1; --i) {
-                uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
-                r -= sbin[c * bt + i];
-                const uint32_t row = lane_off + c;
-#pragma unroll
-                for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
-                low[s] += (row < a.k_low) ? 1u : 0u;
-                hi = c - 1;
-            }
-        }
-        // the number of valid lane subsets in this tile (uniform)
-        const uint64_t first = (uint64_t)lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize;
-        nvalid += (lane_count > first) ? (uint32_t)umin64(lane_count - first, kWaveSize) : 0u;
-    }
-
-    // ---- head range of this tile
-    const uint64_t h0 = (uint64_t)hb * a.heads_per_tile;
-    const uint64_t h1 = umin64(h0 + a.heads_per_tile, head_count);
-    uint64_t remaining = h1 - h0;
-    const uint64_t tile_comb = (uint64_t)nvalid * remaining;
-
-    uint32_t m = 0xffffffffu;                    // full: running minimum of all slots
-    uint32_t ms[SLOTS], cs[SLOTS];               // partial or statistics: per slot
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) { ms[s] = 0xffffffffu; cs[s] = 0; }
-
-    // low-row mask of the head side (partial matrix only)
-    uint64_t head_low_mask = 0;
-    if (PARTIAL) {
-        if (a.k_low > head_off) {
-            uint32_t nl = a.k_low - head_off;
-            head_low_mask = nl >= 64 ? ~0ull : ((1ull << nl) - 1);
-        }
-    }
-
-    auto step = [&](const uint32_t (&H)[W], uint32_t hl) {
-        if (!PARTIAL && !STATS) {
-            uint32_t acc[SLOTS];
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                uint32_t v = bcnt_acc(H[0] ^ P[s][0], pen[s]);
-#pragma unroll
-                for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
-                acc[s] = v;
-            }
-#pragma unroll
-            for (int s = 0; s < SLOTS; s += 2) m = min3u(m, acc[s], acc[s + 1]);
-        } else {
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                uint32_t v = bcnt_acc_s(H[0] ^ P[s][0], hl);
-#pragma unroll
-                for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
-                if (STATS) {
-                    cs[s] = (v < ms[s]) ? 0u : cs[s];
-                    ms[s] = min(ms[s], v);
-                    cs[s] += (v == ms[s]) ? 1u : 0u;
-                } else {
-                    ms[s] = min(ms[s], v);
-                }
-            }
-        }
-    };
-
-    if (head_t == 0) {
-        uint32_t H[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) H[w] = 0;
-        step(H, 0u);
-    } else {
-        // unrank h0 into the head mask (uniform; binomials through the scalar cache)
-        uint64_t x = 0;
-        {
-            uint64_t r = h0;
-            uint32_t hi = head_n - 1;
-            for (uint32_t i = head_t; i >= 1; --i) {
-                uint32_t c = uni(colex_digit_s(binom_c, i, i - 1, hi, r));
-                r -= binom_c[c * (kBinomT + 1) + i];
-                x |= 1ull << c;
-                hi = c - 1;
-            }
-            x = uni64(x);
-        }
-        uint32_t S2[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) S2[w] = 0;
-        {
-            uint64_t rest = x & (x - 1);
-            while (rest) {
-                uint32_t b = (uint32_t)__builtin_ctzll(rest);
-                rest &= rest - 1;
-                cptr32 rp = rows + (head_off + b) * W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) S2[w] ^= rp[w];
-            }
-        }
-        for (;;) {
-            const uint32_t e1 = (uint32_t)__builtin_ctzll(x);
-            const uint64_t xhi = x & (x - 1);
-            const uint32_t e2 = xhi ? (uint32_t)__builtin_ctzll(xhi) : head_n;
-            const uint32_t len = (uint32_t)umin64((uint64_t)(e2 - e1), remaining);
-            uint32_t hl_base = 0;
-            if (PARTIAL) hl_base = (uint32_t)__builtin_popcountll(xhi & head_low_mask);
-            // one row ahead: the device rows carry a zero row after row k-1,
-            // so reading row head_off + e + 1 stays inside the buffer
-            cptr32 rp = rows + (head_off + e1) * W;
-            uint32_t nxt[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) nxt[w] = rp[w];
-            for (uint32_t e = e1; e < e1 + len; ++e) {
-                uint32_t H[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) H[w] = S2[w] ^ nxt[w];
-                rp += W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) nxt[w] = rp[w];
-                uint32_t hl = 0;
-                if (PARTIAL || STATS) {
-                    hl = hl_base;
-                    if (PARTIAL) hl += ((head_low_mask >> e) & 1ull) ? 1u : 0u;
-                }
-                step(H, hl);
-            }
-            remaining -= len;
-            if (remaining == 0) break;
-            // colex successor of the last subset visited, xhi | bit(e2 - 1) (Gosper's step)
-            const uint64_t xl = xhi | (1ull << (e2 - 1));
-            const uint64_t lowbit = xl & (~xl + 1);
-            const uint64_t rr = xl + lowbit;
-            const uint64_t nx = (((rr ^ xl) >> 2) >> __builtin_ctzll(xl)) | rr;
-            uint64_t diff = xhi ^ (nx & (nx - 1));
-            while (diff) {
-                uint32_t b = (uint32_t)__builtin_ctzll(diff);
-                diff &= diff - 1;
-                cptr32 rp = rows + (head_off + b) * W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) S2[w] ^= rp[w];
-            }
-            x = nx;
-        }
-    }
-
-    // ---- end of tile: weights, wave reduction, atomics
-    uint32_t lane_best;
-    uint32_t lane_cnt = 0;
-    if (!PARTIAL && !STATS) {
-        lane_best = m + a.g;                     // identity part of a full-rank Gamma_j
-        if (m >= 0x10000u) lane_best = 0xffffffffu;
-    } else {
-        lane_best = 0xffffffffu;
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            if (pen[s]) continue;
-            // full-rank statistics: head weight hl was 0, add the whole identity part g
-            const uint32_t wgt = PARTIAL ? ms[s] + low[s] : ms[s] + a.g;
-            if (wgt < lane_best) { lane_best = wgt; lane_cnt = STATS ? cs[s] : 0; }
-            else if (STATS && wgt == lane_best) lane_cnt += cs[s];
-        }
-    }
-    const uint32_t tmin = uni(wave_min(lane_best));
-    uint32_t tcnt = 0;
-    if (STATS) tcnt = uni(wave_sum(lane_best == tmin ? lane_cnt : 0u));
-    if (lane == 0) {
-        atomicMin(a.key, ((unsigned long long)tmin << kTileBits) | tile);
-        atomicAdd(a.ncomb, (unsigned long long)tile_comb);
-        if (STATS) stats_merge(a.stats, tmin, tcnt);
-    }
-}
 
 template <int W, int SLOTS, bool PARTIAL, bool STATS>
 __global__ __launch_bounds__(kBlock) void bz_enum_kernel(TaskArgs a) {
