@@ -17,6 +17,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -36,6 +38,45 @@ WORKLOADS = {
 }
 
 
+def batch_comparison(bz, inputs, count: int, cap: float) -> dict:
+    """codes/s of one bz_min_distance_batch call against bz_min_distance per code."""
+    import torch
+
+    from paper_1911_08963_amd import workloads
+    t = time.perf_counter()
+    kept, drawn, est = workloads.select(inputs.batch_code, lambda c: bz.prepare_host(c.G, c.n)[1:3],
+                                        count, cap)
+    objs = [bz.Code(c.G, c.n) for c in kept]
+    setup = time.perf_counter() - t
+    bz.min_distance_batch(objs[: min(64, len(objs))])            # warm-up: code objects, graph path
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs, sts = bz.min_distance_batch(objs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    assert all(s == 0 for s in sts), "batched search failed"
+    t = time.perf_counter()
+    plain = [bz.min_distance(o) for o in objs]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    mism = sum(1 for a, b in zip(outs, plain) if a.d != b.d)
+    assert mism == 0, f"{mism} codes differ between batched and plain"
+    comb = sum(o.combinations for o in outs)
+    print(f"batch: {len(objs)} codes ({drawn} drawn, setup {setup:.1f} s): batched {tb:.3f} s, "
+          f"plain {tp:.3f} s", file=sys.stderr, flush=True)
+    for o in objs:
+        o.close()
+    return {
+        "workload": "batched: random binary codes, n ~ U{48..160}, rho ~ U[0.33, 0.6], k = round(n rho), "
+                    "seeds 1000000+i, kept when the estimated cost is <= cap",
+        "codes": len(objs), "drawn": drawn, "cost_cap": cap, "combinations": comb,
+        "batched_s": tb, "plain_s": tp,
+        "batched_codes_per_s": len(objs) / tb, "plain_codes_per_s": len(objs) / tp,
+        "speedup": tp / tb, "batched_combinations_per_s": comb / tb,
+        "d_histogram": {str(d): int(n) for d, n in zip(*np.unique([o.d for o in outs], return_counts=True))},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +87,10 @@ def main():
     ap.add_argument("--cpu-max-level", type=int, default=6)
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the CPU-oracle sample until this much time has accumulated")
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="codes in the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--batch-cap", type=float, default=1e10,
+                    help="keep batched-workload codes whose estimated cost is at most this")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -136,6 +181,8 @@ def main():
             "avg_combinations_per_launch": comb / launches,
         },
     }
+    if args.batch:
+        line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap)
     if not args.no_cpu:
         import oracle
         t = time.perf_counter()

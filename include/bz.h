@@ -102,7 +102,7 @@ typedef struct {
     void *workspace;            /* caller device memory, or NULL: the library allocates     */
     size_t workspace_bytes;
     volatile const uint32_t *cancel;   /* host-visible word; nonzero cancels (nullable)      */
-    uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8); 0 = tuned choice    */
+    uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8, 16); 0 = by row width */
     uint32_t heads_per_tile;    /* head steps per wave tile; 0 = tuned choice                */
 } bz_opts;
 

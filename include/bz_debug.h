@@ -39,7 +39,7 @@ typedef struct {
 } bz_debug_rect;
 
 /* The tiling the search uses for level g of a Gamma matrix with k rows
- * (slots per lane 2, 4 or 8; heads_per_tile 0 = chosen from target_tiles). */
+ * (slots per lane 2, 4, 8 or 16; heads_per_tile 0 = chosen from target_tiles). */
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                               uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used);

@@ -67,7 +67,6 @@ constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
 constexpr size_t kWsBytes = kWsRects + kMaxRects * sizeof(bz::Rect);
 
-uint32_t default_slots(uint32_t W) { return W <= 4 ? 8u : 4u; }
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
 // later matrices at level g-1 (j == m_f is the partial matrix).
@@ -90,7 +89,6 @@ struct Best {
 
 // ---------------------------------------------------------------- batched search
 
-constexpr uint32_t kBatchSlots = 4;
 constexpr uint64_t kBatchMaxComb = 1ull << 50;   // levels with C(k, g) beyond this get no plan
 constexpr uint64_t kBatchTargetTiles = 64;        // tiles per task aimed at by the planner
 
@@ -101,26 +99,30 @@ struct BatchLayout {
     std::vector<bz::CodeState> states;
     std::vector<bz::PlanEntry> plans;
     std::vector<bz::Rect> rects;
+    std::vector<unsigned long long> log_init;   // initial task-log entries
+    unsigned long long log_ht[3] = {0, 0, 0};    // initial log head, log tail, next code
     uint32_t done_init = 0, grid = 0, stats_total = 0;
+    uint64_t log_cap = 0;
     size_t off_codes = 0, off_states = 0, off_plans = 0, off_rects = 0, off_stats = 0,
-           off_recover = 0, off_dummy = 0, off_done = 0, total = 0;
+           off_recover = 0, off_log = 0, off_done = 0, total = 0;
 };
 
 bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt, int cus, bool stats,
                        BatchLayout &Lo) {
     Lo = BatchLayout{};
-    std::map<uint32_t, std::pair<uint32_t, uint32_t>> plan_of_k;   // k -> (plan_base, g_max)
-    for (uint32_t i = 0; i < count; ++i) {
-        const bz_code *c = codes[i];
-        if (!c) return fail(BZ_EINVAL, "null code in batch");
-        if (plan_of_k.count(c->k)) continue;
+    // plans per (k, slots): (first entry, levels with a plan)
+    std::map<std::pair<uint32_t, uint32_t>, std::pair<uint32_t, uint32_t>> plan_of;
+    auto plans_for = [&](uint32_t k, uint32_t slots) -> std::pair<uint32_t, uint32_t> {
+        auto key = std::make_pair(k, slots);
+        auto it = plan_of.find(key);
+        if (it != plan_of.end()) return it->second;
         const uint32_t base = (uint32_t)Lo.plans.size();
         uint32_t gmax = 0;
-        for (uint32_t g = 1; g <= std::min<uint32_t>(c->k, bz::kBinomT); ++g) {
-            if (bz::binom_sat(c->k, g) >= kBatchMaxComb) break;
+        for (uint32_t g = 1; g <= std::min<uint32_t>(k, bz::kBinomT); ++g) {
+            if (bz::binom_sat(k, g) >= kBatchMaxComb) break;
             bz::LevelPlan p;
             std::string err;
-            if (!bz::plan_level(c->k, g, kBatchSlots, opt.heads_per_tile, kBatchTargetTiles, p, err)) break;
+            if (!bz::plan_level(k, g, slots, opt.heads_per_tile, kBatchTargetTiles, p, err)) break;
             bz::PlanEntry e{};
             e.total_tiles = p.total_tiles;
             e.rect_off = (uint32_t)Lo.rects.size();
@@ -130,8 +132,10 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
             Lo.plans.push_back(e);
             gmax = g;
         }
-        plan_of_k[c->k] = {base, gmax};
-    }
+        return plan_of[key] = {base, gmax};
+    };
+    for (uint32_t i = 0; i < count; ++i)
+        if (!codes[i]) return fail(BZ_EINVAL, "null code in batch");
     for (uint32_t i = 0; i < count; ++i) {
         const bz_code *c = codes[i];
         bz::BatchCode d{};
@@ -139,8 +143,11 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         d.full_rows = (const uint64_t *)((const char *)c->dev + c->dev_full_off);
         d.n = c->n; d.k = c->k; d.m_f = c->num_full; d.k_m = c->partial_rank;
         d.nsets = c->nsets; d.W_full = c->W_full; d.W_partial = c->W_partial;
-        d.plan_base = plan_of_k[c->k].first;
-        d.g_max = plan_of_k[c->k].second;
+        const auto pf = plans_for(c->k, bz::slots_for_w(c->W_full));
+        const auto pp = c->W_partial ? plans_for(c->k, bz::slots_for_w(c->W_partial)) : pf;
+        d.plan_full = pf.first;
+        d.plan_partial = pp.first;
+        d.g_max = std::min(pf.second, pp.second);
         d.stats_off = Lo.stats_total;
         d.stats_cap = c->nsets * std::max<uint32_t>(1, d.g_max);
         Lo.stats_total += d.stats_cap;
@@ -153,20 +160,21 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
             S.L = 1; S.U = 1;
             Lo.done_init++;
         } else {
-            const bz::PlanEntry &P = Lo.plans[d.plan_base];
+            const bz::PlanEntry &P = Lo.plans[d.plan_full];
             S.cursor = 0;
             bz::TaskSlot &t = S.slot[0];
             t.key = ~0ull; t.stats = ~0ull; t.ncomb = 0; t.completed = 0;
-            t.total_tiles = P.total_tiles;
+            t.tiles = P.total_tiles;                          // epoch 0
+            if (P.total_tiles >= 8) Lo.log_init.push_back(((unsigned long long)i << 24) + 1ull);
             t.j = 0; t.g = 1; t.rect_off = P.rect_off; t.nrects = P.nrects;
             t.heads_per_tile = P.heads_per_tile;
             t.exit_at = stats ? 0u : 1u;
             t.u_prev = S.U;
         }
         Lo.states.push_back(S);
+        Lo.log_cap += (uint64_t)d.nsets * std::max<uint32_t>(1, d.g_max) + 1;
     }
     Lo.grid = (uint32_t)std::max(1, cus * bz::batch_blocks_per_cu(stats));
-    const size_t waves = (size_t)Lo.grid * (bz::kBlock / bz::kWaveSize);
     size_t off = 0;
     Lo.off_codes = off; off = align256(off + count * sizeof(bz::BatchCode));
     Lo.off_states = off; off = align256(off + count * sizeof(bz::CodeState));
@@ -174,7 +182,7 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
     Lo.off_rects = off; off = align256(off + Lo.rects.size() * sizeof(bz::Rect));
     Lo.off_stats = off; off = align256(off + (size_t)Lo.stats_total * sizeof(bz::BatchStat));
     Lo.off_recover = off; off = align256(off + count * sizeof(bz::BatchRecover));
-    Lo.off_dummy = off; off = align256(off + waves * bz::kWaveSize * sizeof(unsigned long long));
+    Lo.off_log = off; off = align256(off + (Lo.log_cap + 3) * sizeof(unsigned long long));
     Lo.off_done = off; off = align256(off + sizeof(uint32_t));
     Lo.total = std::max(off, kWsBytes);
     return BZ_OK;
@@ -187,8 +195,8 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     bz_opts opt{};
     if (o) opt = *o;
     if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
-    if (opt.slots_per_lane && opt.slots_per_lane != kBatchSlots)
-        return fail(BZ_EINVAL, "the batched search uses 4 slots per lane");
+    if (opt.slots_per_lane)
+        return fail(BZ_EINVAL, "the batched search chooses slots per lane itself (pass 0)");
     const bool stats = opt.flags & BZ_F_STATS;
     const double t0 = now_s();
     for (uint32_t i = 0; i < count; ++i) {
@@ -238,6 +246,13 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     BZ_HIP(hipMemcpyAsync(ws + Lo.off_rects, Lo.rects.data(), Lo.rects.size() * sizeof(bz::Rect), hipMemcpyHostToDevice, st));
     BZ_HIP(hipMemcpyAsync(ws + Lo.off_done, &done_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
     BZ_HIP(hipMemsetAsync(ws + Lo.off_recover, 0, count * sizeof(bz::BatchRecover), st));
+    // task log: [head, tail, entries...]
+    BZ_HIP(hipMemsetAsync(ws + Lo.off_log, 0, (Lo.log_cap + 3) * sizeof(unsigned long long), st));
+    Lo.log_ht[1] = Lo.log_init.size();
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_log, Lo.log_ht, sizeof(Lo.log_ht), hipMemcpyHostToDevice, st));
+    if (!Lo.log_init.empty())
+        BZ_HIP(hipMemcpyAsync(ws + Lo.off_log + 3 * sizeof(unsigned long long), Lo.log_init.data(),
+                              Lo.log_init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
 
     bz::BatchArgs b{};
     b.codes = (const bz::BatchCode *)(ws + Lo.off_codes);
@@ -247,10 +262,14 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     b.binom = dc.binom;
     b.stats = (bz::BatchStat *)(ws + Lo.off_stats);
     b.recover = (bz::BatchRecover *)(ws + Lo.off_recover);
-    b.dummy = (unsigned long long *)(ws + Lo.off_dummy);
+    b.log_head = (unsigned long long *)(ws + Lo.off_log);
+    b.log_tail = b.log_head + 1;
+    b.next_code = b.log_head + 2;
+    b.log = b.log_head + 3;
+    b.log_cap = Lo.log_cap;
     b.done_count = (unsigned int *)(ws + Lo.off_done);
     b.cancel = (const uint32_t *)opt.cancel;
-    b.ncodes = count; b.flags = opt.flags; b.max_level = opt.max_level; b.slots = kBatchSlots;
+    b.ncodes = count; b.flags = opt.flags; b.max_level = opt.max_level;
 
     // one captured graph: the persistent search, then witness recovery
     hipStream_t cs = nullptr;
@@ -449,8 +468,9 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     res->combinations = 0; res->stats_len = 0; res->launches = 0;
     res->prepare_s = c->prepare_s; res->search_s = 0; res->kernel_s = 0;
     if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
-    if (opt.slots_per_lane && opt.slots_per_lane != 2 && opt.slots_per_lane != 4 && opt.slots_per_lane != 8)
-        return fail(BZ_EINVAL, "slots_per_lane must be 0, 2, 4 or 8");
+    if (opt.slots_per_lane && opt.slots_per_lane != 2 && opt.slots_per_lane != 4 && opt.slots_per_lane != 8 &&
+        opt.slots_per_lane != 16)
+        return fail(BZ_EINVAL, "slots_per_lane must be 0, 2, 4, 8 or 16");
     const bool stats = opt.flags & BZ_F_STATS, level_stop = opt.flags & BZ_F_LEVEL_STOP;
     const bool want_witness = !(opt.flags & BZ_F_NO_WITNESS) && res->witness;
     const uint32_t n = c->n, k = c->k, m_f = c->num_full, k_m = c->partial_rank;
@@ -519,7 +539,8 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         for (uint32_t j = 0; j < c->nsets && !done; ++j) {
             if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
             const uint32_t W = c->W(j);
-            const uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : (stats ? 4u : default_slots(W));
+            const uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
+            if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
             auto key = std::make_pair(g, slots);
             if (!plans.count(key)) {
                 std::string err;
@@ -670,7 +691,7 @@ bz_status bz_debug_prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint3
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                               uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used) {
-    if (k == 0 || k > (uint32_t)bz::kMaxN || (slots != 2 && slots != 4 && slots != 8))
+    if (k == 0 || k > (uint32_t)bz::kMaxN || (slots != 2 && slots != 4 && slots != 8 && slots != 16))
         return fail(BZ_EINVAL, "bad k or slots");
     bz::LevelPlan p;
     std::string err;

@@ -3,21 +3,31 @@
 // codes at once.
 //
 // Every code has one current task, (Gamma_j, g), at a time. Its tiles are
-// handed out by a cursor word (epoch << 40 | next tile); a wave claims one tile
-// with a CAS on that word, runs the same tile code as the single-code kernel
+// handed out by a cursor word (epoch << 40 | next tile): a wave claims one tile
+// with a fetch-add on that word and keeps it if the slot of that epoch says the
+// tile exists. It runs the same tile code as the single-code kernel
 // (bz_tile.h) and then counts the tile as finished. The wave that finishes a
 // task's last tile advances the code on the device: it records the task's
 // statistics, moves U, applies the certified lower bound, and either
 // publishes the next task (the other of the code's two task slots, then a
-// release store of the new epoch) or marks the code finished. This is the
-// coordinator/worker scheme of the paper's dynamic algorithms (Sec. 3.2)
-// collapsed into one GPU: the coordinator is whichever wave finishes last.
-// Waves leave when every code is finished or the cancel word is set.
+// release store of the new epoch, then an entry at the end of the task log)
+// or marks the code finished. This is the coordinator/worker scheme of the
+// paper's dynamic algorithms (Sec. 3.2) collapsed into one GPU: the
+// coordinator is whichever wave finishes last.
 //
-// Atomics whose result the wave needs are issued by all 64 lanes: lane 0 on
-// the real word, the other lanes on per-wave scratch words. The wave then
-// reads lane 0's result with readfirstlane, with no lane-dependent branch
-// around it.
+// Finding work: every code being searched has an owner, the wave that
+// finished its last task, which goes straight on with the next task. A wave
+// without a code first takes an unstarted one (a counter over the batch);
+// when none is left it helps: tasks with at least kShareTiles tiles are also
+// appended to a shared task log, which helpers walk from its head, moving the
+// head past exhausted entries. So every helper converges on the oldest large
+// task, and small tasks never leave their owner. Idle waves back off
+// exponentially. Waves leave when every code is finished or the cancel word is
+// set.
+//
+// Atomics whose result the wave needs are issued by all 64 lanes on the same
+// word, with only lane 0 contributing (see wave_fetch_add64): no lane-dependent
+// branch surrounds the readfirstlane that broadcasts the result.
 #include <hip/hip_runtime.h>
 
 #include "bz_internal.h"
@@ -26,21 +36,21 @@
 
 namespace bz {
 
-__device__ __forceinline__ bool wave_cas64(unsigned long long *p, unsigned long long expect,
-                                           unsigned long long desired, unsigned long long *dummy,
-                                           uint32_t lane) {
-    unsigned long long *addr = lane == 0 ? p : dummy + lane;
-    unsigned long long e = expect;
-    bool ok = __hip_atomic_compare_exchange_strong(addr, &e, desired, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-    return uni(ok ? 1u : 0u) != 0u;
+constexpr uint64_t kShareTiles = 8;   // tasks with this many tiles are offered to helpers
+
+// Wave-level atomics without a lane-dependent branch: every lane targets the
+// same word, only lane 0 contributes a value, and the compiler's atomic
+// optimizer folds the wave into one memory operation. Lane 0's return value is
+// the word's old value, which readfirstlane hands to the whole wave.
+__device__ __forceinline__ unsigned long long wave_fetch_add64(unsigned long long *p, unsigned long long v,
+                                                               uint32_t lane) {
+    const unsigned long long mine = lane == 0 ? v : 0ull;
+    unsigned long long old = __hip_atomic_fetch_add(p, mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return uni64(old);
 }
 
-__device__ __forceinline__ unsigned long long wave_fetch_add64(unsigned long long *p, unsigned long long v,
-                                                               unsigned long long *dummy, uint32_t lane) {
-    unsigned long long *addr = lane == 0 ? p : dummy + lane;
-    unsigned long long old = __hip_atomic_fetch_add(addr, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    return uni64(old);
+__device__ __forceinline__ void wave_fetch_max64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
@@ -55,7 +65,7 @@ __device__ __forceinline__ uint32_t certified_bound(uint32_t j, uint32_t g, uint
     return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)(e > 0 ? e : 0);
 }
 
-template <int SLOTS, bool STATS>
+template <bool STATS>
 __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, uint64_t epoch, uint64_t tile,
                                            uint32_t lane, cptr64 binom_c) {
     const BatchCode &D = b.codes[code];
@@ -78,7 +88,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     a.k_low = partial ? uni(D.k_m) : k;
     a.g = g;
     a.heads_per_tile = uni(s->heads_per_tile);
-    a.total_tiles = uni64(s->total_tiles);
+    a.total_tiles = uni64(s->tiles) & kCursorMask;
     a.u_prev = uni(s->u_prev);
     a.exit_at = uni(s->exit_at);
     if (a.exit_at) {
@@ -92,8 +102,12 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     constexpr uint32_t BT = kBinomT + 1;
     switch (W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
-    case WW * 2: run_tile<WW, SLOTS, false, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane); break; \
-    case WW * 2 + 1: run_tile<WW, SLOTS, true, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane); break;
+    case WW * 2:                                                                                      \
+        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane);    \
+        break;                                                                                        \
+    case WW * 2 + 1:                                                                                  \
+        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane);     \
+        break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
     default: break;
@@ -165,17 +179,18 @@ __device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch,
         S->have_best = have_best; S->best_j = best_j; S->best_g = best_g; S->best_tile = best_tile;
         S->combinations = combos; S->last_level = last_level; S->status = status;
         if (!done) {
-            const PlanEntry P = b.plans[D.plan_base + ng - 1];
+            const PlanEntry P = b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1];
             TaskSlot *n = &S->slot[(epoch + 1) & 1];
             n->key = ~0ull;
             n->stats = ~0ull;
             n->ncomb = 0;
             n->completed = 0;
-            n->total_tiles = P.total_tiles;
             n->j = nj; n->g = ng;
             n->rect_off = P.rect_off; n->nrects = P.nrects; n->heads_per_tile = P.heads_per_tile;
             n->exit_at = STATS ? 0u : Lcert;
             n->u_prev = U;
+            __hip_atomic_store(&n->tiles, (unsigned long long)(((epoch + 1) << kEpochShift) | P.total_tiles),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&S->cursor, (unsigned long long)((epoch + 1) << kEpochShift), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -184,15 +199,53 @@ __device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch,
             __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    if (!done && uni64(b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1].total_tiles) >= kShareTiles) {
+        const unsigned long long pos = wave_fetch_add64(b.log_tail, 1ull, lane);
+        if (lane == 0 && pos < b.log_cap)
+            __hip_atomic_store(b.log + pos, (unsigned long long)((((uint64_t)code) << 24) | (epoch + 1)) + 1ull,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
-template <int SLOTS, bool STATS>
+// Claims one tile of the code's current task: (true, epoch, tile) on success.
+__device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uint32_t lane, uint64_t &epoch,
+                                          uint64_t &tile) {
+    CodeState *S = b.state + code;
+    const unsigned long long w0 = uni64(__hip_atomic_load(&S->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t e0 = w0 >> kEpochShift;
+    if (e0 == kDoneEpoch) return false;
+    const unsigned long long tw0 =
+        uni64(__hip_atomic_load(&S->slot[e0 & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
+    const unsigned long long w = wave_fetch_add64(&S->cursor, 1ull, lane);
+    const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
+    if (e == kDoneEpoch) return false;
+    const unsigned long long tw =
+        uni64(__hip_atomic_load(&S->slot[e & 1].tiles, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+    if ((tw >> kEpochShift) != e || t >= (tw & kCursorMask)) return false;
+    epoch = e;
+    tile = t;
+    return true;
+}
+
+// Whether a log entry's task can no longer hand out tiles.
+__device__ __forceinline__ bool entry_exhausted(const BatchArgs &b, uint32_t code, uint64_t ep) {
+    CodeState *S = b.state + code;
+    const unsigned long long w = uni64(__hip_atomic_load(&S->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t e = w >> kEpochShift;
+    if (e == kDoneEpoch || e != ep) return true;
+    const unsigned long long tw =
+        uni64(__hip_atomic_load(&S->slot[e & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return (tw >> kEpochShift) == e && (w & kCursorMask) >= (tw & kCursorMask);
+}
+
+template <bool STATS>
 __global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
-    const uint32_t wave = blockIdx.x * (blockDim.x / kWaveSize) + uni(threadIdx.x / kWaveSize);
-    unsigned long long *dummy = b.dummy + (size_t)wave * kWaveSize;
     cptr64 binom_c = (cptr64)b.binom;
-    uint32_t c = wave % b.ncodes;
+    constexpr uint32_t kNone = 0xffffffffu;
+    uint32_t cur = kNone;                              // the code this wave owns or helps
+    uint32_t idle = 0;                                 // consecutive rounds without work
     for (;;) {
         const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
         if (dc >= b.ncodes) break;
@@ -200,35 +253,59 @@ __global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
             uint32_t cv = __hip_atomic_load(b.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             if (uni(cv)) break;
         }
-        // find a code with a tile to hand out, starting from the last one served
         bool got = false;
         uint32_t code = 0;
         uint64_t epoch = 0, tile = 0;
-        for (uint32_t p = 0; p < b.ncodes && !got; ++p) {
-            uint32_t cc = c + p;
-            if (cc >= b.ncodes) cc -= b.ncodes;
-            CodeState *S = b.state + cc;
-            const unsigned long long w =
-                uni64(__hip_atomic_load(&S->cursor, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-            const uint64_t e = w >> kEpochShift;
-            if (e == kDoneEpoch) continue;
-            const uint64_t t = w & kCursorMask;
-            const uint64_t T = uni64(__hip_atomic_load(&S->slot[e & 1].total_tiles, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT));
-            if (t >= T) continue;
-            if (wave_cas64(&S->cursor, w, w + 1, dummy, lane)) {
-                got = true; code = cc; epoch = e; tile = t;
+        if (cur != kNone) {
+            got = try_claim(b, cur, lane, epoch, tile);
+            if (got) code = cur; else cur = kNone;
+        }
+        // an unstarted code
+        while (!got && uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < b.ncodes) {
+            const unsigned long long nc = wave_fetch_add64(b.next_code, 1ull, lane);
+            if (nc >= b.ncodes) break;
+            if (try_claim(b, (uint32_t)nc, lane, epoch, tile)) {
+                got = true;
+                code = cur = (uint32_t)nc;
             }
         }
         if (!got) {
-            __builtin_amdgcn_s_sleep(16);
+            // help with the oldest large task in the log
+            uint64_t q = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const uint64_t tail =
+                uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            const uint64_t end = tail < b.log_cap ? tail : b.log_cap;
+            for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
+                const unsigned long long ent =
+                    uni64(__hip_atomic_load(b.log + q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                if (ent == 0) break;                              // being written
+                const uint32_t cc = (uint32_t)((ent - 1) >> 24);
+                const uint64_t ep = (ent - 1) & ((1ull << 24) - 1);
+                if (entry_exhausted(b, cc, ep)) {
+                    // move the shared head past it (it only ever moves forward)
+                    if (q == uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                        wave_fetch_max64(b.log_head, q + 1);
+                    continue;
+                }
+                if (try_claim(b, cc, lane, epoch, tile)) {
+                    got = true;
+                    code = cur = cc;
+                }
+            }
+        }
+        if (!got) {
+            // exponential back-off (up to ~110 us): idle waves must not crowd the
+            // few cache lines the working waves claim and complete tiles on
+            const uint32_t rounds = 1u << (idle < 5 ? idle : 5);
+            for (uint32_t r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
+            ++idle;
             continue;
         }
-        c = code;
-        batch_tile<SLOTS, STATS>(b, code, epoch, tile, lane, binom_c);
+        idle = 0;
+        batch_tile<STATS>(b, code, epoch, tile, lane, binom_c);
         TaskSlot *s = &b.state[code].slot[epoch & 1];
-        const uint64_t T = uni64(s->total_tiles);
-        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, dummy, lane);
+        const uint64_t T = uni64(s->tiles) & kCursorMask;
+        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, lane);
         if (prev + 1 == T) batch_advance<STATS>(b, code, epoch, lane);
     }
 }
@@ -238,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
 // steps, builds the head sum from scratch, and compares every lane sum
 // against the target weight. The first match writes the row indices and the
 // codeword (XOR of the full rows).
-constexpr int kRecoverLanes = kWaveSize * 8;
+constexpr int kRecoverLanes = kWaveSize * 16;
 
 __device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, uint32_t off, uint32_t nside,
                                 uint32_t *idx) {
@@ -272,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
     const uint32_t k_low = partial ? D.k_m : k;
     const uint32_t *rows = D.rows + (size_t)(partial ? D.m_f : j) * (k + 1) * D.W_full;
     const uint64_t *full = D.full_rows + (size_t)j * k * kHostWords;
-    const PlanEntry P = b.plans[D.plan_base + g - 1];
+    const PlanEntry P = b.plans[(partial ? D.plan_partial : D.plan_full) + g - 1];
     const Rect *rects = b.rects + P.rect_off;
     const uint64_t tile = S->best_tile;
     uint32_t lo = 0, hi = P.nrects - 1;
@@ -283,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
     const Rect R = rects[lo];
     const uint64_t local = tile - R.tile_begin;
     const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
-    const uint32_t lane_items = kWaveSize * b.slots;
+    const uint32_t lane_items = kWaveSize * slots_for_w(W);
     const uint64_t q0 = lb * lane_items;
     const uint32_t nl = (uint32_t)((R.lane_count - q0) < lane_items ? (R.lane_count - q0) : lane_items);
     const uint64_t h0 = hb * P.heads_per_tile;
@@ -338,21 +415,20 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
     }
 }
 
-template <int SLOTS, bool STATS>
+template <bool STATS>
 static hipError_t launch_batch_t(const BatchArgs &b, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((bz_batch_kernel<SLOTS, STATS>), dim3(grid), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL((bz_batch_kernel<STATS>), dim3(grid), dim3(kBlock), 0, st, b);
     return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st) {
-    if (b.slots != 4) return hipErrorInvalidValue;
-    return stats ? launch_batch_t<4, true>(b, grid, st) : launch_batch_t<4, false>(b, grid, st);
+    return stats ? launch_batch_t<true>(b, grid, st) : launch_batch_t<false>(b, grid, st);
 }
 
 int batch_blocks_per_cu(bool stats) {
     int n = 0;
-    hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<4, true>, kBlock, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<4, false>, kBlock, 0);
+    hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<true>, kBlock, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<false>, kBlock, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 

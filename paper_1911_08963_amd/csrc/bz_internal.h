@@ -22,6 +22,11 @@ constexpr int kBlock = 256;              // threads per work-group (4 waves)
 
 using HostRow = std::array<uint64_t, kHostWords>;
 
+// Combinations each lane keeps per head step, by 32-bit words per row: enough
+// that one head step carries 40-70 VALU operations, so the scalar head
+// stepping (and its colex carries) stays well below the vector work.
+constexpr uint32_t slots_for_w(uint32_t W) { return W <= 2 ? 16u : (W <= 4 ? 8u : 4u); }
+
 // One product of two colex subset spaces inside the g-subsets of [0, k):
 // every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a
 // head_t-subset of [head_off, head_off + head_n). The two ranges are disjoint.

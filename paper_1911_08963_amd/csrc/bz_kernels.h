@@ -52,8 +52,9 @@ struct BatchCode {
     const uint64_t *full_rows;   // Gamma_j full rows at j * k * kHostWords
     uint32_t n, k, m_f, k_m;
     uint32_t nsets, W_full, W_partial, g_max;   // plans exist for levels 1..g_max
-    uint32_t plan_base;          // plan of level g is plans[plan_base + g - 1]
-    uint32_t stats_off, stats_cap, _pad;
+    uint32_t plan_full;          // plan of level g for a full-rank Gamma_j: plans[plan_full + g - 1]
+    uint32_t plan_partial;       // the same for the partial Gamma_m (its slot count may differ)
+    uint32_t stats_off, stats_cap;
 };
 
 // One task of one code; two per code, selected by the parity of the epoch.
@@ -62,7 +63,7 @@ struct alignas(64) TaskSlot {
     unsigned long long stats;     // (min << 55) | count
     unsigned long long ncomb;     // combinations enumerated
     unsigned long long completed; // tiles finished
-    uint64_t total_tiles;
+    unsigned long long tiles;     // (epoch << 40) | tile count: which task this slot holds
     uint32_t j, g, rect_off, nrects, heads_per_tile, exit_at;
     uint32_t u_prev, _pad[3];
 };
@@ -100,10 +101,14 @@ struct BatchArgs {
     const uint64_t *binom;
     BatchStat *stats;
     BatchRecover *recover;
-    unsigned long long *dummy;    // 64 words per wave: targets of the lanes other than lane 0
+    unsigned long long *log;      // published tasks, (code << 24 | epoch) + 1, append-only
+    unsigned long long *log_head; // entries before it are exhausted
+    unsigned long long *log_tail; // next free entry
+    unsigned long long *next_code;// codes not yet started: next index to hand out
     unsigned int *done_count;
     const uint32_t *cancel;
-    uint32_t ncodes, flags, max_level, slots;
+    uint64_t log_cap;             // entries the log can hold (bounds every publication)
+    uint32_t ncodes, flags, max_level, _pad;
 };
 
 hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st);

@@ -144,6 +144,9 @@ static hipError_t launch_w(const TaskArgs &a, uint32_t slots, bool partial, bool
     case 2: return launch_ws<W, 2>(a, partial, stats, grid, lds, st);
     case 4: return launch_ws<W, 4>(a, partial, stats, grid, lds, st);
     case 8: return launch_ws<W, 8>(a, partial, stats, grid, lds, st);
+    case 16:
+        if constexpr (W <= 4) return launch_ws<W, 16>(a, partial, stats, grid, lds, st);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }

@@ -316,7 +316,9 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
     uint32_t tcnt = 0;
     if (STATS) tcnt = uni(wave_sum(lane_best == tmin ? lane_cnt : 0u));
     if (lane == 0) {
-        atomicMin(a.key, ((unsigned long long)tmin << kTileBits) | tile);
+        // most tiles do not lower the key: read it first, update only when needed
+        const unsigned long long mine = ((unsigned long long)tmin << kTileBits) | tile;
+        if (mine < __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(a.key, mine);
         atomicAdd(a.ncomb, (unsigned long long)tile_comb);
         if (STATS) stats_merge(a.stats, tmin, tcnt);
     }

@@ -97,7 +97,7 @@ def test_tilings_agree(bz):
         n = int(rng.integers(40, 90))
         k = int(rng.integers(14, 26))
         G = _rand(rng, n, k, systematic=bool(t % 2))
-        for slots, heads in [(2, 0), (4, 0), (8, 0), (2, 1), (8, 3), (4, 7)]:
+        for slots, heads in [(2, 0), (4, 0), (8, 0), (16, 0), (2, 1), (8, 3), (4, 7), (16, 5)]:
             _compare(bz, G, n, slots=slots, heads=heads, tag=f"tiling{t}")
 
 

@@ -116,7 +116,7 @@ def _rect_subsets(r):
             yield tuple(sorted(a + b))
 
 
-@pytest.mark.parametrize("slots", [2, 8])
+@pytest.mark.parametrize("slots", [2, 8, 16])
 def test_plan_covers_every_subset_once(slots):
     for k in list(range(1, 15)) + [17, 20]:
         for g in range(1, k + 1):
@@ -129,7 +129,7 @@ def test_plan_covers_every_subset_once(slots):
 
 @pytest.mark.parametrize("k,g", [(64, 7), (64, 11), (96, 12), (150, 9), (200, 6), (256, 8), (40, 20)])
 def test_plan_invariants(k, g):
-    for slots in (2, 4, 8):
+    for slots in (2, 4, 8, 16):
         rects, tiles, ht = bz.plan_level(k, g, slots=slots)
         tot = 0
         tb = 0
