@@ -56,9 +56,13 @@ typedef struct bz_code bz_code;   /* opaque; immutable after bz_prepare */
  * scans the columns in their natural order. */
 typedef struct {
     uint32_t perm_trials;
-    uint32_t _reserved;
+    uint32_t flags;             /* BZ_PREPARE_HOST_ONLY: keep Gamma_j on the host only */
     uint64_t perm_seed;
 } bz_prepare_opts;
+
+/* A host-only code makes no device allocation and no device copy; only a
+ * server (bz_server_submit) can search it, which copies Gamma_j itself. */
+#define BZ_PREPARE_HOST_ONLY 1u
 
 /* Sec. 2.1, information sets and the systematic matrices Gamma_j.
  * Copies G (k rows of ld_words uint64, layout above); the caller keeps G.
@@ -66,7 +70,9 @@ typedef struct {
  * S_2 the first basis of the remaining columns, and so on, while the remaining
  * columns still have rank k. The last columns have rank k_m < k. Gamma_j is
  * the reduced echelon form of G with S_j's columns first. Gamma_j's
- * non-identity columns are uploaded to the current HIP device.
+ * non-identity columns are uploaded to the current HIP device (not for
+ * BZ_PREPARE_HOST_ONLY). bz_min_distance and bz_min_distance_batch refuse a
+ * host-only code (EINVAL).
  * Errors: EINVAL (G or out null, k == 0, k > n, n > BZ_MAX_N,
  * ld_words < ceil(n/64)); ERANK (rank(G) < k); ENOMEM; EDEVICE. */
 bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_words,
@@ -146,6 +152,68 @@ bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
  * to codes[i]. Returns the first per-code error, or BZ_OK. */
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
                                 bz_result *res, bz_status *per_code);
+
+/* ---- Serving: a resident search that admits requests while it runs.
+ *
+ * Continuous batching of many searches on one device (the dynamic
+ * coordinator/worker scheme of Sec. 3.2, with the GPU's waves as workers).
+ * bz_server_create launches one persistent kernel that stays on the device
+ * until bz_server_destroy. Each bz_server_submit stages one code's Gamma_j in
+ * pinned host memory and publishes it at once: a wave of the running kernel
+ * copies it onto the device and starts its level loop beside the requests
+ * already there, and idle waves help with the largest task of any request.
+ * Every request runs the same Alg. 1 bookkeeping as bz_min_distance_batch,
+ * so its result does not depend on what else runs.
+ *
+ * Admission: a request takes one of `slots` request slots and dev_bytes of
+ * the HBM budget until it is polled. Without a free slot or budget, submit
+ * returns BZ_EBUSY and the caller retries after bz_server_poll. Device data of
+ * finished requests is recycled by draining the server and relaunching the
+ * kernel (submit returns BZ_EBUSY until the requests in flight are done).
+ *
+ * While a server runs it holds every compute unit of its device: other
+ * libbz searches on that device wait until it is destroyed.
+ * A server is used by one thread at a time (calls are serialized inside).
+ */
+typedef struct bz_server bz_server;
+
+typedef struct {
+    uint32_t slots;             /* requests in flight at most (1..65536; 0 = 1024)                 */
+    uint32_t flags;             /* BZ_F_STATS: statistics mode for every request                   */
+    size_t hbm_budget;          /* device bytes in-flight requests may hold (0 = no limit)         */
+    uint32_t stats_cap;         /* task records kept per request (0 = 512)                         */
+    uint32_t target_tiles;      /* tiles per task aimed at by the planner (0 = 512)                */
+    size_t arena_bytes;         /* device bytes for Gamma_j of one kernel launch (0 = 1 GiB)       */
+    uint32_t codes_per_launch;  /* requests per kernel launch before a relaunch (0 = 1 << 20)      */
+    uint32_t _reserved;
+} bz_server_opts;
+
+/* Creates a server on the current HIP device and launches its kernel on a
+ * stream of its own. Errors: EINVAL, ENOMEM, EDEVICE. */
+bz_status bz_server_create(const bz_server_opts *o /* nullable */, bz_server **out);
+
+/* Submits one search. o: flags BZ_F_LEVEL_STOP / BZ_F_NO_WITNESS, and BZ_F_STATS
+ * exactly as the server was created; max_level. The other bz_opts fields are
+ * ignored. The code may be freed after the call. res (with its witness and
+ * stats buffers) must stay valid until bz_server_poll returns its ticket; then
+ * it holds what bz_min_distance would give, search_s being the time from
+ * submission to completion. Errors: EINVAL, EBUSY (no slot, budget or ring
+ * entry free: poll, then retry), ENOMEM (plan tables full), EDEVICE. */
+bz_status bz_server_submit(bz_server *s, const bz_code *code, const bz_opts *o, bz_result *res,
+                           uint64_t *ticket);
+
+/* Collects finished requests: fills their bz_result and writes up to cap
+ * (ticket, status) pairs, in completion order; *n_done is their number. */
+bz_status bz_server_poll(bz_server *s, uint64_t *tickets, bz_status *statuses, uint32_t cap,
+                         uint32_t *n_done);
+
+/* Requests submitted and not yet polled. */
+bz_status bz_server_pending(bz_server *s, uint32_t *pending);
+
+/* Lets the published requests finish, stops the kernel and frees everything.
+ * Results not polled are dropped. Returns EDEVICE if the kernel had to be
+ * stopped (after timeout_s seconds; 0 = 60) before the requests finished. */
+bz_status bz_server_destroy(bz_server *s, double timeout_s);
 
 const char *bz_status_str(bz_status s);
 const char *bz_last_error(void);

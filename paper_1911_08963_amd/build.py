@@ -9,13 +9,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbz.so")
-SOURCES = ["bz_api.cpp", "bz_prepare.cpp", "bz_plan.cpp", "bz_kernels.hip", "bz_batch.hip"]
+SOURCES = ["bz_api.cpp", "bz_prepare.cpp", "bz_plan.cpp", "bz_kernels.hip", "bz_batch.hip",
+           "bz_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-pthread",
 ]
 
 

@@ -26,8 +26,11 @@ P = ctypes.POINTER
 
 
 class PrepareOpts(ctypes.Structure):
-    _fields_ = [("perm_trials", ctypes.c_uint32), ("_reserved", ctypes.c_uint32),
+    _fields_ = [("perm_trials", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("perm_seed", ctypes.c_uint64)]
+
+
+BZ_PREPARE_HOST_ONLY = 1
 
 
 class CodeInfo(ctypes.Structure):
@@ -69,6 +72,13 @@ class DebugRect(ctypes.Structure):
                 ("head_blocks", ctypes.c_uint64), ("_reserved2", ctypes.c_uint64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_size_t), ("stats_cap", ctypes.c_uint32),
+                ("target_tiles", ctypes.c_uint32), ("arena_bytes", ctypes.c_size_t),
+                ("codes_per_launch", ctypes.c_uint32), ("_reserved", ctypes.c_uint32)]
+
+
 class BZError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -88,6 +98,11 @@ def _signatures(lib):
         "bz_min_distance_batch": ([P(vp), u32, P(Opts), P(Result), P(ctypes.c_int)], ctypes.c_int),
         "bz_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "bz_last_error": ([], ctypes.c_char_p),
+        "bz_server_create": ([P(ServerOpts), P(vp)], ctypes.c_int),
+        "bz_server_submit": ([vp, vp, P(Opts), P(Result), P(u64)], ctypes.c_int),
+        "bz_server_poll": ([vp, P(u64), P(ctypes.c_int), u32, P(u32)], ctypes.c_int),
+        "bz_server_pending": ([vp, P(u32)], ctypes.c_int),
+        "bz_server_destroy": ([vp, ctypes.c_double], ctypes.c_int),
         "bz_debug_prepare_host": ([P(u64), u32, u32, u32, P(u32), P(u32), P(ctypes.c_int32),
                                    P(u64), u32, P(u32), ctypes.c_size_t], ctypes.c_int),
         "bz_debug_plan_level": ([u32, u32, u32, u32, u64, P(DebugRect), u32, P(u32), P(u64),
@@ -127,14 +142,15 @@ def _words(G) -> np.ndarray:
 
 
 class Code:
-    """A prepared code (bz_prepare): information sets and Gamma_j on the current device."""
+    """A prepared code (bz_prepare): information sets and Gamma_j on the current device
+    (host_only: on the host only, for a Server)."""
 
-    def __init__(self, G, n: int, perm_trials: int = 0, perm_seed: int = 0):
+    def __init__(self, G, n: int, perm_trials: int = 0, perm_seed: int = 0, host_only: bool = False):
         G = _words(G)
         k, ld = G.shape
         self.n, self.k = int(n), int(k)
         h = ctypes.c_void_p()
-        po = PrepareOpts(perm_trials, 0, perm_seed)
+        po = PrepareOpts(perm_trials, BZ_PREPARE_HOST_ONLY if host_only else 0, perm_seed)
         _check(lib().bz_prepare(G.ctypes.data_as(P(ctypes.c_uint64)), k, n, ld, ctypes.byref(po),
                                 ctypes.byref(h)))
         self._h = h
@@ -286,6 +302,115 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
             o_.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
         outs.append(o_)
     return outs, [per[i] for i in range(cnt)]
+
+
+# ---------------------------------------------------------------- serving
+
+def _fill(st, r, wit, stb, n, stats_cap) -> SearchResult:
+    out = SearchResult(st, r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,
+                       wit[: (n + 63) // 64].copy(), [], r.launches, r.prepare_s, r.search_s,
+                       r.kernel_s)
+    for t in range(min(r.stats_len, stats_cap)):
+        s = stb[t]
+        out.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
+    return out
+
+
+class Server:
+    """bz_server_*: a resident search on the current device that admits requests as they come.
+
+    submit() returns a ticket, or None when the server is busy (no slot or HBM
+    budget; poll and retry). poll() returns finished requests as
+    (ticket, SearchResult) pairs; search_s is the time from submission to
+    completion seen by the library's watcher thread.
+    """
+
+    def __init__(self, *, slots: int = 1024, stats: bool = False, hbm_budget: int = 0,
+                 stats_cap: int = 512, target_tiles: int = 0, arena_bytes: int = 0,
+                 codes_per_launch: int = 0):
+        o = ServerOpts(slots, BZ_F_STATS if stats else 0, hbm_budget, stats_cap, target_tiles,
+                       arena_bytes, codes_per_launch, 0)
+        h = ctypes.c_void_p()
+        _check(lib().bz_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.stats = stats
+        self.stats_cap = stats_cap
+        self._live = {}                     # ticket -> (Result, witness, stats buffer, n)
+        self._done = {}                     # finished, collected by wait() for later
+
+    def submit(self, code: Code, *, level_stop: bool = False, witness: bool = True,
+               max_level: int = 0):
+        flags = (BZ_F_STATS if self.stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
+            (0 if witness else BZ_F_NO_WITNESS)
+        o = _opts(flags, max_level, None, None, None, 0, 0)
+        r = Result()
+        wit = np.zeros(4, dtype=np.uint64)
+        stb = (LevelStat * self.stats_cap)()
+        r.witness = wit.ctypes.data_as(P(ctypes.c_uint64))
+        r.stats = stb
+        r.stats_cap = self.stats_cap
+        t = ctypes.c_uint64()
+        st = lib().bz_server_submit(self._h, code.handle, ctypes.byref(o), ctypes.byref(r), ctypes.byref(t))
+        if st == BZ_EBUSY:
+            return None
+        _check(st)
+        self._live[t.value] = (r, wit, stb, code.n)
+        return t.value
+
+    def poll(self, cap: int = 4096):
+        if self._done:
+            out = list(self._done.items())
+            self._done.clear()
+            return out + self._poll(cap)
+        return self._poll(cap)
+
+    def _poll(self, cap: int):
+        tk = (ctypes.c_uint64 * cap)()
+        sts = (ctypes.c_int * cap)()
+        nd = ctypes.c_uint32()
+        _check(lib().bz_server_poll(self._h, tk, sts, cap, ctypes.byref(nd)))
+        out = []
+        for i in range(nd.value):
+            r, wit, stb, n = self._live.pop(tk[i])
+            out.append((tk[i], _fill(sts[i], r, wit, stb, n, self.stats_cap)))
+        return out
+
+    def pending(self) -> int:
+        p = ctypes.c_uint32()
+        _check(lib().bz_server_pending(self._h, ctypes.byref(p)))
+        return p.value
+
+    def wait(self, ticket: int, timeout: float = 60.0):
+        """Polls until the ticket is done; other finished requests are kept for later polls."""
+        import time
+        t0 = time.perf_counter()
+        while True:
+            for t, res in self._poll(4096):
+                self._done[t] = res
+            if ticket in self._done:
+                return self._done.pop(ticket)
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(50e-6)
+
+    def close(self, timeout: float = 60.0) -> int:
+        st = BZ_OK
+        if getattr(self, "_h", None):
+            st = lib().bz_server_destroy(self._h, timeout)
+            self._h = None
+        return st
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- host-only inspection

@@ -11,10 +11,11 @@
 #include <string>
 #include <vector>
 
+#include "bz_host.h"
 #include "bz_internal.h"
 #include "bz_kernels.h"
 
-namespace {
+namespace bz {
 
 thread_local std::string g_err;
 
@@ -23,23 +24,12 @@ bz_status fail(bz_status s, const std::string &msg) {
     return s;
 }
 
-#define BZ_HIP(call)                                                                      \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess) return fail(BZ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Per-device constants: the binomial table and the compute-unit count.
-struct DeviceConst {
-    uint64_t *binom = nullptr;
-    int cus = 0;
-};
-std::mutex g_mu;
-std::map<int, DeviceConst> g_devconst;
+static std::mutex g_mu;
+static std::map<int, DeviceConst> g_devconst;
 
 bz_status device_const(int dev, DeviceConst &out) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -57,6 +47,16 @@ bz_status device_const(int dev, DeviceConst &out) {
     out = dc;
     return BZ_OK;
 }
+
+}  // namespace bz
+
+namespace {
+
+using bz::DeviceConst;
+using bz::device_const;
+using bz::fail;
+using bz::g_err;
+using bz::now_s;
 
 // Workspace layout of one search (bytes).
 constexpr size_t kWsTask = 0;          // key, stats, ncomb, tile counter (u64 each)
@@ -117,21 +117,8 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         auto it = plan_of.find(key);
         if (it != plan_of.end()) return it->second;
         const uint32_t base = (uint32_t)Lo.plans.size();
-        uint32_t gmax = 0;
-        for (uint32_t g = 1; g <= std::min<uint32_t>(k, bz::kBinomT); ++g) {
-            if (bz::binom_sat(k, g) >= kBatchMaxComb) break;
-            bz::LevelPlan p;
-            std::string err;
-            if (!bz::plan_level(k, g, slots, opt.heads_per_tile, kBatchTargetTiles, p, err)) break;
-            bz::PlanEntry e{};
-            e.total_tiles = p.total_tiles;
-            e.rect_off = (uint32_t)Lo.rects.size();
-            e.nrects = (uint32_t)p.rects.size();
-            e.heads_per_tile = p.heads_per_tile;
-            Lo.rects.insert(Lo.rects.end(), p.rects.begin(), p.rects.end());
-            Lo.plans.push_back(e);
-            gmax = g;
-        }
+        const uint32_t gmax = bz::build_level_plans(k, slots, opt.heads_per_tile, kBatchTargetTiles, kBatchMaxComb,
+                                                    0, Lo.plans, Lo.rects);
         return plan_of[key] = {base, gmax};
     };
     for (uint32_t i = 0; i < count; ++i)
@@ -150,6 +137,8 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         d.g_max = std::min(pf.second, pp.second);
         d.stats_off = Lo.stats_total;
         d.stats_cap = c->nsets * std::max<uint32_t>(1, d.g_max);
+        d.flags = opt.flags;
+        d.max_level = opt.max_level;
         Lo.stats_total += d.stats_cap;
         Lo.codes.push_back(d);
         bz::CodeState S{};
@@ -205,6 +194,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
         res[i].combinations = 0; res[i].stats_len = 0; res[i].launches = 0;
         res[i].search_s = 0; res[i].kernel_s = 0;
         if (!codes[i]) return fail(BZ_EINVAL, "null code in batch");
+        if (!codes[i]->dev) return fail(BZ_EINVAL, "host-only code in batch (BZ_PREPARE_HOST_ONLY)");
         res[i].prepare_s = codes[i]->prepare_s;
         if (codes[i]->device != codes[0]->device) return fail(BZ_EINVAL, "codes of a batch must be on one device");
     }
@@ -269,7 +259,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     b.log_cap = Lo.log_cap;
     b.done_count = (unsigned int *)(ws + Lo.off_done);
     b.cancel = (const uint32_t *)opt.cancel;
-    b.ncodes = count; b.flags = opt.flags; b.max_level = opt.max_level;
+    b.ncodes = count;
 
     // one captured graph: the persistent search, then witness recovery
     hipStream_t cs = nullptr;
@@ -391,6 +381,7 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
     bz_status st = bz::prepare_host(G, k, n, ld_words, opts, *c, err);
     if (st != BZ_OK) return fail(st, err);
     BZ_HIP(hipGetDevice(&c->device));
+    const bool host_only = opts && (opts->flags & BZ_PREPARE_HOST_ONLY);
     // device layout: per matrix (k + 1) x W dwords (the last row zero), then
     // the full rows at a 256-byte boundary
     std::vector<uint32_t> dev_packed;
@@ -407,6 +398,11 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
     size_t pbytes = (dev_packed.size() * sizeof(uint32_t) + 255) & ~(size_t)255;
     c->dev_full_off = pbytes;
     c->dev_bytes = pbytes + c->full_rows.size() * sizeof(bz::HostRow);
+    if (host_only) {
+        c->prepare_s = now_s() - t0;
+        *out = c.release();
+        return BZ_OK;
+    }
     if (hipMalloc(&c->dev, c->dev_bytes) != hipSuccess) return fail(BZ_ENOMEM, "device allocation for Gamma_j");
     hipError_t e1 = hipMemcpy(c->dev, dev_packed.data(), dev_packed.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy((char *)c->dev + pbytes, c->full_rows.data(),
@@ -462,6 +458,7 @@ bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opt
 
 bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     if (!c || !res) return fail(BZ_EINVAL, "null argument");
+    if (!c->dev) return fail(BZ_EINVAL, "code prepared host-only (BZ_PREPARE_HOST_ONLY): submit it to a server");
     bz_opts opt{};
     if (o) opt = *o;
     res->d = 0; res->lower_bound = 0; res->upper_bound = 0; res->last_level = 0;

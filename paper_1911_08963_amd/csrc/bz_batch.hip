@@ -114,15 +114,33 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     }
 }
 
+template <bool STATS>
+__device__ void serve_finish(const ServeArgs &sv, uint32_t code, uint32_t lane, uint32_t status, uint32_t U,
+                             uint32_t L, uint32_t last_level, uint32_t nstats, uint64_t combos, uint32_t best_j,
+                             uint32_t best_g, uint64_t best_tile, bool have_best);
+
+// Appends (code, epoch) to the shared task log unless the ring is full.
+__device__ __forceinline__ void log_append(const BatchArgs &b, uint32_t code, uint64_t epoch, uint32_t lane) {
+    const uint64_t head = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t tail = uni64(__hip_atomic_load(b.log_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (tail - head >= b.log_cap) return;          // full: the owner runs the task alone
+    const unsigned long long pos = wave_fetch_add64(b.log_tail, 1ull, lane);
+    if (lane == 0)
+        __hip_atomic_store(b.log + pos % b.log_cap, (unsigned long long)((((uint64_t)code) << 24) | epoch) + 1ull,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The last wave of a task: bookkeeping of Alg. 1 for one code, then the next
 // task or the end. All values are uniform; lane 0 does the stores.
-template <bool STATS>
-__device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch, uint32_t lane) {
+template <bool STATS, bool SERVE>
+__device__ void batch_advance(const BatchArgs &b, const ServeArgs *sv, uint32_t code, uint64_t epoch,
+                              uint32_t lane) {
     CodeState *S = &b.state[code];
     const BatchCode &D = b.codes[code];
     TaskSlot *s = &S->slot[epoch & 1];
     const uint32_t j = uni(s->j), g = uni(s->g);
     const uint32_t k = uni(D.k), m_f = uni(D.m_f), k_m = uni(D.k_m), nsets = uni(D.nsets);
+    const uint32_t flags = uni(D.flags), max_level = uni(D.max_level);
     const unsigned long long key = uni64(__hip_atomic_load(&s->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long sw = uni64(__hip_atomic_load(&s->stats, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long nc = uni64(__hip_atomic_load(&s->ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -158,7 +176,7 @@ __device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch,
         const uint32_t Lc = certified_bound(j, g, m_f, k_m, k);
         Lcert = max(Lcert, Lc);
         // per-Gamma stop: check after every matrix; Alg. 1 as printed: only once a level is done
-        const bool check = !(b.flags & BZ_F_LEVEL_STOP) || j + 1 == nsets;
+        const bool check = !(flags & BZ_F_LEVEL_STOP) || j + 1 == nsets;
         if (check) L = max(L, Lc);
         if (check && L >= U) {
             done = true;
@@ -167,7 +185,7 @@ __device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch,
             if (nj == nsets) { nj = 0; ng = g + 1; }
             if (ng > k) {
                 done = true;                                  // everything enumerated: d = U
-            } else if (ng > uni(D.g_max) || (b.max_level && ng > b.max_level)) {
+            } else if (ng > uni(D.g_max) || (max_level && ng > max_level)) {
                 done = true;
                 status = (uint32_t)(int32_t)BZ_ELIMIT;
             }
@@ -196,15 +214,16 @@ __device__ void batch_advance(const BatchArgs &b, uint32_t code, uint64_t epoch,
         } else {
             __hip_atomic_store(&S->cursor, (unsigned long long)(kDoneEpoch << kEpochShift), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (!SERVE) __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    if (!done && uni64(b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1].total_tiles) >= kShareTiles) {
-        const unsigned long long pos = wave_fetch_add64(b.log_tail, 1ull, lane);
-        if (lane == 0 && pos < b.log_cap)
-            __hip_atomic_store(b.log + pos, (unsigned long long)((((uint64_t)code) << 24) | (epoch + 1)) + 1ull,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (SERVE && done) {
+        serve_finish<STATS>(*sv, code, lane, status, U, L, last_level, nstats, combos, best_j, best_g, best_tile,
+                            have_best != 0);
+        if (lane == 0) __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (!done && uni64(b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1].total_tiles) >= kShareTiles)
+        log_append(b, code, epoch + 1, lane);
 }
 
 // Claims one tile of the code's current task: (true, epoch, tile) on success.
@@ -239,84 +258,24 @@ __device__ __forceinline__ bool entry_exhausted(const BatchArgs &b, uint32_t cod
     return (tw >> kEpochShift) == e && (w & kCursorMask) >= (tw & kCursorMask);
 }
 
-template <bool STATS>
-__global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
-    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
-    cptr64 binom_c = (cptr64)b.binom;
-    constexpr uint32_t kNone = 0xffffffffu;
-    uint32_t cur = kNone;                              // the code this wave owns or helps
-    uint32_t idle = 0;                                 // consecutive rounds without work
-    for (;;) {
-        const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-        if (dc >= b.ncodes) break;
-        if (b.cancel) {
-            uint32_t cv = __hip_atomic_load(b.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (uni(cv)) break;
+// XORs into cw the full rows of the t elements of the colex rank r (t-subsets
+// of [off, off + nside)).
+__device__ void unrank_xor(const uint64_t *binom, uint64_t r, uint32_t t, uint32_t off, uint32_t nside,
+                           const uint64_t *full, uint64_t (&cw)[kHostWords]) {
+    uint32_t hi = nside - 1;
+    for (uint32_t i = t; i >= 1; --i) {
+        uint32_t lo = i - 1, c = hi;
+        while (lo < c) {
+            uint32_t mid = (lo + c + 1) >> 1;
+            if (binom[mid * (kBinomT + 1) + i] <= r) lo = mid; else c = mid - 1;
         }
-        bool got = false;
-        uint32_t code = 0;
-        uint64_t epoch = 0, tile = 0;
-        if (cur != kNone) {
-            got = try_claim(b, cur, lane, epoch, tile);
-            if (got) code = cur; else cur = kNone;
-        }
-        // an unstarted code
-        while (!got && uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < b.ncodes) {
-            const unsigned long long nc = wave_fetch_add64(b.next_code, 1ull, lane);
-            if (nc >= b.ncodes) break;
-            if (try_claim(b, (uint32_t)nc, lane, epoch, tile)) {
-                got = true;
-                code = cur = (uint32_t)nc;
-            }
-        }
-        if (!got) {
-            // help with the oldest large task in the log
-            uint64_t q = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            const uint64_t tail =
-                uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-            const uint64_t end = tail < b.log_cap ? tail : b.log_cap;
-            for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
-                const unsigned long long ent =
-                    uni64(__hip_atomic_load(b.log + q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-                if (ent == 0) break;                              // being written
-                const uint32_t cc = (uint32_t)((ent - 1) >> 24);
-                const uint64_t ep = (ent - 1) & ((1ull << 24) - 1);
-                if (entry_exhausted(b, cc, ep)) {
-                    // move the shared head past it (it only ever moves forward)
-                    if (q == uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-                        wave_fetch_max64(b.log_head, q + 1);
-                    continue;
-                }
-                if (try_claim(b, cc, lane, epoch, tile)) {
-                    got = true;
-                    code = cur = cc;
-                }
-            }
-        }
-        if (!got) {
-            // exponential back-off (up to ~110 us): idle waves must not crowd the
-            // few cache lines the working waves claim and complete tiles on
-            const uint32_t rounds = 1u << (idle < 5 ? idle : 5);
-            for (uint32_t r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
-            ++idle;
-            continue;
-        }
-        idle = 0;
-        batch_tile<STATS>(b, code, epoch, tile, lane, binom_c);
-        TaskSlot *s = &b.state[code].slot[epoch & 1];
-        const uint64_t T = uni64(s->tiles) & kCursorMask;
-        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, lane);
-        if (prev + 1 == T) batch_advance<STATS>(b, code, epoch, lane);
+        r -= binom[lo * (kBinomT + 1) + i];
+        for (int w = 0; w < kHostWords; ++w) cw[w] ^= full[(size_t)(off + lo) * kHostWords + w];
+        hi = lo - 1;
     }
 }
 
-// Witness of each finished code: one work-group per code re-scans the winning
-// tile. Its lane subsets' sums go to LDS first; then every thread takes head
-// steps, builds the head sum from scratch, and compares every lane sum
-// against the target weight. The first match writes the row indices and the
-// codeword (XOR of the full rows).
-constexpr int kRecoverLanes = kWaveSize * 16;
-
+// Writes the t elements of the colex rank r (t-subsets of [off, off + nside)) into idx.
 __device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, uint32_t off, uint32_t nside,
                                 uint32_t *idx) {
     uint32_t hi = nside - 1;
@@ -332,6 +291,338 @@ __device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, u
     }
     return t;
 }
+
+// ---- serving
+
+__device__ __forceinline__ uint64_t sys_load64(const void *p) {
+    return __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t sys_load32(const void *p) {
+    return __hip_atomic_load((const uint32_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void sys_store64(void *p, uint64_t v) {
+    __hip_atomic_store((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void sys_store32(void *p, uint32_t v) {
+    __hip_atomic_store((uint32_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Copies `words` 64-bit words from pinned host memory to device memory, all lanes.
+__device__ __forceinline__ void wave_copy_in(uint64_t *dst, const uint64_t *src, uint64_t words, uint32_t lane) {
+    constexpr uint32_t kUnroll = 4;
+    uint64_t i = lane;
+    for (; i + (kUnroll - 1) * kWaveSize < words; i += kUnroll * kWaveSize) {
+        uint64_t v[kUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) v[u] = sys_load64(src + i + u * kWaveSize);
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) dst[i + u * kWaveSize] = v[u];
+    }
+    for (; i < words; i += kWaveSize) dst[i] = sys_load64(src + i);
+}
+
+constexpr uint64_t kPollTicks = 500;          // wall-clock ticks between polls of the host words (5 us at 100 MHz)
+
+// The wave's view of the host's published count and shutdown word. Device
+// copies are read every time; at most one wave per kPollTicks reads the host
+// words (pinned memory across the bus) and refreshes them.
+__device__ __forceinline__ void serve_view(const ServeArgs &sv, uint32_t lane, uint64_t &pub, uint32_t &stop) {
+    unsigned long long *v = sv.view;
+    stop = uni((uint32_t)__hip_atomic_load(v + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+    pub = uni64(__hip_atomic_load(v + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t now = uni64(wall_clock64());
+    const uint64_t last = uni64(__hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (now - last <= kPollTicks || now < last) return;
+    const unsigned long long mine = lane == 0 ? now : 0ull;
+    const uint64_t old = uni64(__hip_atomic_fetch_max(v, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (now - old <= kPollTicks || now < old) return;     // another wave polls
+    // the host raises published before it sets shutdown: read them in the other order
+    const uint32_t s = uni(__hip_atomic_load(sv.shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+    const uint64_t p = uni64(__hip_atomic_load(sv.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+    __hip_atomic_fetch_max(v + 1, lane == 0 ? (unsigned long long)p : 0ull, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (s && lane == 0) __hip_atomic_store(v + 2, (unsigned long long)s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (p > pub) pub = p;
+    if (s > stop) stop = s;
+}
+
+// The wave holding ticket t brings request t onto the device: payload, new
+// plan tables, the code's description and its first task. The request's code
+// index is its ticket. Returns false (nothing started) only when told to stop
+// at once while waiting for another request's plan tables.
+template <bool STATS>
+__device__ bool serve_start(const ServeArgs &sv, uint64_t ticket, uint32_t lane) {
+    const BatchArgs &b = sv.b;
+    const ServeReq *R = sv.reqs + ticket % sv.ring;
+    const uint32_t slot = (uint32_t)ticket;
+    const uint64_t *src = (const uint64_t *)uni64(sys_load64(&R->src));
+    uint64_t *dst = (uint64_t *)uni64(sys_load64(&R->dst));
+    const uint64_t words = uni64(sys_load64(&R->words));
+    wave_copy_in(dst, src, words, lane);
+    // the code description (BatchCode is a whole number of 64-bit words)
+    static_assert(sizeof(BatchCode) % 8 == 0, "BatchCode is copied as 64-bit words");
+    wave_copy_in((uint64_t *)(b.codes + slot), (const uint64_t *)&R->code, sizeof(BatchCode) / 8, lane);
+    for (int p = 0; p < 2; ++p) {
+        const uint32_t pid = uni(sys_load32(&R->plan_copy[p]));
+        if (pid == kNoPlan) continue;
+        const ServePlanDesc *pd = sv.plan_desc + pid;
+        const uint32_t eo = uni(sys_load32(&pd->entry_off)), lv = uni(sys_load32(&pd->levels));
+        const uint32_t ro = uni(sys_load32(&pd->rect_off)), nr = uni(sys_load32(&pd->nrects));
+        static_assert(sizeof(PlanEntry) % 8 == 0 && sizeof(Rect) % 8 == 0, "plan tables copy as words");
+        wave_copy_in((uint64_t *)(b.plans + eo), (const uint64_t *)(sv.host_plans + eo),
+                     (uint64_t)lv * sizeof(PlanEntry) / 8, lane);
+        wave_copy_in((uint64_t *)(b.rects + ro), (const uint64_t *)(sv.host_rects + ro),
+                     (uint64_t)nr * sizeof(Rect) / 8, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(sv.plan_ready + pid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int p = 0; p < 2; ++p) {
+        const uint32_t pid = uni(sys_load32(&R->plan_wait[p]));
+        if (pid == kNoPlan) continue;
+        // copied in by the wave of an earlier ticket, which never waits on a later one
+        while (!uni(__hip_atomic_load(sv.plan_ready + pid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))) {
+            if (uni(__hip_atomic_load(sv.shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) >= 2) return false;
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    const BatchCode &D = b.codes[slot];
+    const uint32_t n = uni(D.n), k = uni(D.k);
+    CodeState *S = b.state + slot;
+    const uint32_t U0 = n - k + 1;
+    if (k == n) {
+        // the whole space: d = 1, no enumeration
+        if (lane == 0) {
+            S->U = 1; S->L = 1; S->Lcert = 1; S->status = 0; S->last_level = 0; S->nstats = 0;
+            S->have_best = 0; S->best_j = 0; S->best_g = 0; S->best_tile = 0; S->combinations = 0;
+            __hip_atomic_store(&S->cursor, (unsigned long long)(kDoneEpoch << kEpochShift), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        serve_finish<STATS>(sv, slot, lane, 0u, 1u, 1u, 0u, 0u, 0ull, 0u, 0u, 0ull, false);
+        if (lane == 0) __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    const PlanEntry P = b.plans[uni(D.plan_full)];
+    if (lane == 0) {
+        S->U = U0; S->L = 1; S->Lcert = 1; S->status = 0; S->last_level = 1; S->nstats = 0;
+        S->have_best = 0; S->best_j = 0; S->best_g = 0; S->best_tile = 0; S->combinations = 0;
+        TaskSlot *t = &S->slot[0];
+        t->key = ~0ull; t->stats = ~0ull; t->ncomb = 0; t->completed = 0;
+        t->j = 0; t->g = 1; t->rect_off = P.rect_off; t->nrects = P.nrects; t->heads_per_tile = P.heads_per_tile;
+        t->exit_at = STATS ? 0u : 1u;
+        t->u_prev = U0;
+        __hip_atomic_store(&t->tiles, (unsigned long long)P.total_tiles, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&S->cursor, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (uni64(P.total_tiles) >= kShareTiles) log_append(b, slot, 0, lane);
+    return true;
+}
+
+// The persistent loop shared by the batch (a fixed set of codes, started
+// through a counter) and the server (requests published while it runs,
+// started by the wave holding their ticket).
+template <bool STATS, bool SERVE>
+__device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *sv) {
+    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
+    cptr64 binom_c = (cptr64)b.binom;
+    constexpr uint32_t kNone = 0xffffffffu;
+    constexpr uint64_t kNoTicket = ~0ull;
+    uint32_t cur = kNone;                              // the code this wave owns or helps
+    uint32_t idle = 0;                                 // consecutive rounds without work
+    uint64_t ticket = kNoTicket;                       // serving: the request this wave will start
+    for (;;) {
+        uint64_t pub = 0;
+        if (SERVE) {
+            uint32_t stop = 0;
+            serve_view(*sv, lane, pub, stop);
+            if (stop >= 2) break;
+            if (stop == 1 &&
+                uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) >= pub)
+                break;
+        } else {
+            const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            if (dc >= b.ncodes) break;
+            if (b.cancel) {
+                uint32_t cv = __hip_atomic_load(b.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (uni(cv)) break;
+            }
+        }
+        bool got = false;
+        uint32_t code = 0;
+        uint64_t epoch = 0, tile = 0;
+        if (SERVE && ticket != kNoTicket && ticket < pub) {
+            // a new request first: its latency starts at publication
+            const bool started = serve_start<STATS>(*sv, ticket, lane);
+            const uint32_t c = (uint32_t)ticket;
+            ticket = kNoTicket;
+            if (!started) continue;                    // stopping: the loop's top leaves
+            if (try_claim(b, c, lane, epoch, tile)) {
+                got = true;
+                code = cur = c;
+            }
+        }
+        if (!got && cur != kNone) {
+            got = try_claim(b, cur, lane, epoch, tile);
+            if (got) code = cur; else cur = kNone;
+        }
+        if (SERVE) {
+            if (!got && ticket == kNoTicket) {
+                // tickets past the launch's capacity are never published
+                ticket = wave_fetch_add64(b.next_code, 1ull, lane);
+                if (ticket < pub) continue;
+            }
+        } else {
+            // an unstarted code
+            while (!got &&
+                   uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < b.ncodes) {
+                const unsigned long long nc = wave_fetch_add64(b.next_code, 1ull, lane);
+                if (nc >= b.ncodes) break;
+                if (try_claim(b, (uint32_t)nc, lane, epoch, tile)) {
+                    got = true;
+                    code = cur = (uint32_t)nc;
+                }
+            }
+        }
+        if (!got) {
+            // help with the oldest large task in the log
+            uint64_t q = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const uint64_t end =
+                uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
+                const unsigned long long ent = uni64(
+                    __hip_atomic_load(b.log + q % b.log_cap, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                if (ent == 0) break;                              // being written
+                const uint32_t cc = (uint32_t)((ent - 1) >> 24);
+                const uint64_t ep = (ent - 1) & ((1ull << 24) - 1);
+                if (cc >= b.ncodes || entry_exhausted(b, cc, ep)) {
+                    // move the shared head past it (it only ever moves forward)
+                    if (q == uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                        wave_fetch_max64(b.log_head, q + 1);
+                    continue;
+                }
+                if (try_claim(b, cc, lane, epoch, tile)) {
+                    got = true;
+                    code = cur = cc;
+                }
+            }
+        }
+        if (!got) {
+            // exponential back-off (batch: up to ~110 us, serving: ~27 us): idle
+            // waves must not crowd the few cache lines the working waves claim
+            // and complete tiles on
+            constexpr uint32_t kMaxShift = SERVE ? 3 : 5;
+            const uint32_t rounds = 1u << (idle < kMaxShift ? idle : kMaxShift);
+            for (uint32_t r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
+            ++idle;
+            continue;
+        }
+        idle = 0;
+        batch_tile<STATS>(b, code, epoch, tile, lane, binom_c);
+        TaskSlot *s = &b.state[code].slot[epoch & 1];
+        const uint64_t T = uni64(s->tiles) & kCursorMask;
+        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, lane);
+        if (prev + 1 == T) batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
+    }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
+    queue_loop<STATS, false>(b, nullptr);
+}
+
+// The arguments live in device memory: passed by value, their address
+// (taken by the rare paths) would force a copy into per-lane scratch.
+template <bool STATS>
+__global__ __launch_bounds__(kBlock) void bz_serve_kernel(const ServeArgs *__restrict__ sv) {
+    queue_loop<STATS, true>(sv->b, sv);
+}
+
+// A finished request: its statistics and witness (found by this wave in the
+// winning tile) go to its completion record in host memory, flag last.
+template <bool STATS>
+__device__ void serve_finish(const ServeArgs &sv, uint32_t code, uint32_t lane, uint32_t status, uint32_t U,
+                             uint32_t L, uint32_t last_level, uint32_t nstats, uint64_t combos, uint32_t best_j,
+                             uint32_t best_g, uint64_t best_tile, bool have_best) {
+    const BatchArgs &b = sv.b;
+    const BatchCode &D = b.codes[code];
+    const uint32_t hs = uni(D.slot);
+    ServeRecord *rec = sv.records + hs;
+    // task statistics: device copy -> host, three words per entry
+    {
+        static_assert(sizeof(BatchStat) == 24, "BatchStat is three words");
+        const uint32_t ns = min(nstats, uni(D.stats_cap));
+        const uint64_t *from = (const uint64_t *)(b.stats + uni(D.stats_off));
+        uint64_t *to = (uint64_t *)(sv.host_stats + (size_t)hs * sv.stats_cap);
+        for (uint32_t i = lane; i < ns * 3; i += kWaveSize) sys_store64(to + i, from[i]);
+    }
+    uint64_t cw[kHostWords] = {0, 0, 0, 0};
+    uint32_t st = status;
+    const uint32_t k = uni(D.k), n = uni(D.n);
+    if (st == 0 && k == n) {
+        // d = 1: any row of Gamma_1
+        for (int w = 0; w < kHostWords; ++w) cw[w] = D.full_rows[w];
+    } else if (st == 0 && have_best && !(uni(D.flags) & BZ_F_NO_WITNESS)) {
+        const uint32_t m_f = uni(D.m_f);
+        const bool partial = best_j >= m_f;
+        const uint32_t W = uni(partial ? D.W_partial : D.W_full);
+        const uint32_t *rows = D.rows + (size_t)(partial ? m_f : best_j) * (k + 1) * uni(D.W_full);
+        const PlanEntry P = b.plans[(partial ? D.plan_partial : D.plan_full) + best_g - 1];
+        TaskArgs a{};
+        a.rows = rows;
+        a.rects = b.rects + P.rect_off;
+        a.nrects = P.nrects;
+        a.k = k;
+        a.k_low = partial ? uni(D.k_m) : k;
+        a.g = best_g;
+        a.heads_per_tile = P.heads_per_tile;
+        cptr32 rc = (cptr32)rows;
+        cptr64 binom_c = (cptr64)b.binom;
+        cptr_rect rp = (cptr_rect)a.rects;
+        TileGeom t{};
+        uint64_t q = 0, h = 0;
+        bool found = false;
+        switch (W) {
+#define BZ_FIND(WW)                                                                                            \
+    case WW:                                                                                                   \
+        found = find_in_tile<WW, slots_for_w(WW)>(a, rc, binom_c, rows, b.binom, kBinomT + 1, rp, best_tile,   \
+                                                  lane, U, t, q, h);                                           \
+        break;
+            BZ_FIND(1) BZ_FIND(2) BZ_FIND(3) BZ_FIND(4) BZ_FIND(5) BZ_FIND(6) BZ_FIND(7) BZ_FIND(8)
+#undef BZ_FIND
+        default: break;
+        }
+        if (found) {
+            const uint64_t *full = D.full_rows + (size_t)best_j * k * kHostWords;
+            unrank_xor(b.binom, q, t.lane_t, t.lane_off, t.lane_n, full, cw);
+            if (t.head_t) unrank_xor(b.binom, h, t.head_t, t.head_off, t.head_n, full, cw);
+        } else {
+            st = (uint32_t)(int32_t)BZ_EDEVICE;
+        }
+    }
+    if (lane == 0) {
+        sys_store32(&rec->status, st);
+        sys_store32(&rec->d, st == 0 ? U : 0u);
+        sys_store32(&rec->lower_bound, L);
+        sys_store32(&rec->upper_bound, U);
+        sys_store32(&rec->last_level, last_level);
+        sys_store32(&rec->nstats, nstats);
+        sys_store64(&rec->ticket, D.tag);
+        sys_store64(&rec->combinations, combos);
+        sys_store64(&rec->t_done, wall_clock64());
+        for (int w = 0; w < kHostWords; ++w) sys_store64(&rec->witness[w], cw[w]);
+    }
+    // every lane's stores (the statistics) before the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0) __hip_atomic_store(&rec->flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Witness of each finished code: one work-group per code re-scans the winning
+// tile. Its lane subsets' sums go to LDS first; then every thread takes head
+// steps, builds the head sum from scratch, and compares every lane sum
+// against the target weight. The first match writes the row indices and the
+// codeword (XOR of the full rows).
+constexpr int kRecoverLanes = kWaveSize * 16;
+
 
 __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
     __shared__ uint32_t sP[kRecoverLanes * kMaxW];
@@ -423,6 +714,23 @@ static hipError_t launch_batch_t(const BatchArgs &b, uint32_t grid, hipStream_t 
 
 hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st) {
     return stats ? launch_batch_t<true>(b, grid, st) : launch_batch_t<false>(b, grid, st);
+}
+
+template <bool STATS>
+static hipError_t launch_serve_t(const ServeArgs *sv, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL((bz_serve_kernel<STATS>), dim3(grid), dim3(kBlock), 0, st, sv);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const ServeArgs *sv, uint32_t grid, bool stats, hipStream_t st) {
+    return stats ? launch_serve_t<true>(sv, grid, st) : launch_serve_t<false>(sv, grid, st);
+}
+
+int serve_blocks_per_cu(bool stats) {
+    int n = 0;
+    hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_serve_kernel<true>, kBlock, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_serve_kernel<false>, kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 int batch_blocks_per_cu(bool stats) {

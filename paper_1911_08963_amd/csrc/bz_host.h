@@ -1,0 +1,40 @@
+// Host-side helpers shared by the C ABI's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include <vector>
+
+#include "bz_internal.h"
+#include "bz_kernels.h"
+
+namespace bz {
+
+extern thread_local std::string g_err;       // the message bz_last_error returns
+
+bz_status fail(bz_status s, const std::string &msg);
+double now_s();                               // steady clock, seconds
+
+// Per-device constants: the binomial table and the compute-unit count.
+struct DeviceConst {
+    uint64_t *binom = nullptr;
+    int cus = 0;
+};
+bz_status device_const(int dev, DeviceConst &out);
+
+// Plans of levels 1, 2, ... for one (k, slots): appends one PlanEntry per level
+// (rect_off counted from rect_base + the rects already in `rects`) while
+// C(k, g) < max_comb. Returns the last level planned.
+uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, uint64_t target_tiles,
+                           uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
+                           std::vector<Rect> &rects);
+
+}  // namespace bz
+
+#define BZ_HIP(call)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (call);                                                                             \
+        if (e_ != hipSuccess) return bz::fail(BZ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)

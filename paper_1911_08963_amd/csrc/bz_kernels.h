@@ -46,8 +46,9 @@ struct PlanEntry {
 };
 static_assert(sizeof(PlanEntry) == 32, "PlanEntry is 32 bytes");
 
-// Immutable description of one code of a batch.
-struct BatchCode {
+// Immutable description of one code of a batch. Whole scalar-cache lines:
+// a server writes the entry of a new code while its neighbours are read.
+struct alignas(64) BatchCode {
     const uint32_t *rows;        // packed rows: Gamma_j at j * (k + 1) * W_full, Gamma_m after them
     const uint64_t *full_rows;   // Gamma_j full rows at j * k * kHostWords
     uint32_t n, k, m_f, k_m;
@@ -55,7 +56,11 @@ struct BatchCode {
     uint32_t plan_full;          // plan of level g for a full-rank Gamma_j: plans[plan_full + g - 1]
     uint32_t plan_partial;       // the same for the partial Gamma_m (its slot count may differ)
     uint32_t stats_off, stats_cap;
+    uint32_t flags, max_level;   // BZ_F_LEVEL_STOP; stop after this level (0 = no limit)
+    uint64_t tag;                // serving: the request's ticket
+    uint32_t slot, _pad;         // serving: the completion record and statistics slot
 };
+static_assert(sizeof(BatchCode) % 64 == 0, "BatchCode fills whole cache lines");
 
 // One task of one code; two per code, selected by the parity of the epoch.
 struct alignas(64) TaskSlot {
@@ -107,9 +112,66 @@ struct BatchArgs {
     unsigned long long *next_code;// codes not yet started: next index to hand out
     unsigned int *done_count;
     const uint32_t *cancel;
-    uint64_t log_cap;             // entries the log can hold (bounds every publication)
-    uint32_t ncodes, flags, max_level, _pad;
+    uint64_t log_cap;             // ring size of the log (entry q lives at q % log_cap)
+    uint32_t ncodes, _pad[3];
 };
+
+// ---- serving: a resident search that admits codes while it runs
+//
+// The host stages each request in pinned host memory and publishes it by
+// raising a ticket count; the wave that holds the ticket copies the request
+// onto the device itself, so nothing but the resident kernel writes the device
+// memory it reads while it runs. Within one launch the code index of a request
+// is its ticket and its device data sits at addresses no earlier request
+// used: Gamma_j rows are read through the scalar cache, which a running kernel
+// never invalidates. The host relaunches the kernel to recycle them.
+
+constexpr uint32_t kNoPlan = 0xffffffffu;
+
+struct ServeReq {                 // one published request (ring entry ticket % ring)
+    BatchCode code;               // pointers already into the request's device region
+    const uint64_t *src;          // payload in pinned host memory: packed rows, then full rows
+    uint64_t *dst;                // the request's device region
+    uint64_t words;               // payload length in 64-bit words
+    uint32_t plan_copy[2];        // plans whose tables this request copies in (kNoPlan = none)
+    uint32_t plan_wait[2];        // plans copied in by an earlier request (kNoPlan = none)
+};
+
+struct ServePlanDesc {            // where plan p lives in the plan and rectangle tables
+    uint32_t entry_off, levels, rect_off, nrects;
+};
+
+// Completion record of one request slot, in pinned host memory; the device writes it
+// with system-scope stores and sets flag last.
+struct ServeRecord {
+    uint32_t flag;                // 1 once every other field is final
+    int32_t status;
+    uint32_t d, lower_bound, upper_bound, last_level, nstats, _pad;
+    uint64_t ticket;
+    uint64_t combinations;
+    uint64_t t_done;              // device wall clock at completion
+    uint64_t witness[kHostWords];
+};
+
+struct ServeArgs {
+    BatchArgs b;                  // codes / state: one entry per ticket of this launch; ncodes = capacity
+    const ServeReq *reqs;         // pinned ring of staged requests
+    const ServePlanDesc *plan_desc;   // pinned
+    const PlanEntry *host_plans;  // pinned mirror of the plan table
+    const Rect *host_rects;       // pinned mirror of the rectangle table
+    unsigned int *plan_ready;     // device: nonzero once plan p's tables are copied in
+    const unsigned long long *published;   // pinned: tickets below it are staged
+    const uint32_t *shutdown;     // pinned: 1 = finish the published requests and leave, 2 = leave now
+    ServeRecord *records;         // pinned, one per slot
+    BatchStat *host_stats;        // pinned, stats_cap per slot
+    unsigned long long *view;     // device: [last poll time, published seen, shutdown seen]
+    uint64_t ring;                // entries of reqs
+    uint32_t stats_cap, _pad;
+};
+
+// sv: device memory holding the arguments, unchanged while the kernel runs
+hipError_t launch_serve(const ServeArgs *sv, uint32_t grid, bool stats, hipStream_t st);
+int serve_blocks_per_cu(bool stats);
 
 hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st);
 hipError_t launch_batch_recover(const BatchArgs &b, hipStream_t st);

@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "bz_internal.h"
+#include "bz_kernels.h"
 
 namespace bz {
 namespace {
@@ -113,6 +114,27 @@ bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
         if (ht >= (1u << 24)) { err = "level too large for the tile index"; return false; }
         ht <<= 1;
     }
+}
+
+uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, uint64_t target_tiles,
+                           uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
+                           std::vector<Rect> &rects) {
+    uint32_t gmax = 0;
+    for (uint32_t g = 1; g <= std::min<uint32_t>(k, kBinomT); ++g) {
+        if (binom_sat(k, g) >= max_comb) break;
+        LevelPlan p;
+        std::string err;
+        if (!plan_level(k, g, slots, heads_per_tile, target_tiles, p, err)) break;
+        PlanEntry e{};
+        e.total_tiles = p.total_tiles;
+        e.rect_off = rect_base + (uint32_t)rects.size();
+        e.nrects = (uint32_t)p.rects.size();
+        e.heads_per_tile = p.heads_per_tile;
+        rects.insert(rects.end(), p.rects.begin(), p.rects.end());
+        plans.push_back(e);
+        gmax = g;
+    }
+    return gmax;
 }
 
 }  // namespace bz

@@ -86,6 +86,7 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
     if (k == 0 || k > n || n > (uint32_t)kMaxN) { err = "need 0 < k <= n <= BZ_MAX_N"; return BZ_EINVAL; }
     if (ld < (n + 63) / 64) { err = "ld_words < ceil(n/64)"; return BZ_EINVAL; }
     if (opts && opts->perm_trials > 1) { err = "column-permutation search is not implemented"; return BZ_EINVAL; }
+    if (opts && (opts->flags & ~(uint32_t)BZ_PREPARE_HOST_ONLY)) { err = "unknown prepare flag"; return BZ_EINVAL; }
 
     std::vector<HostRow> rows(k);
     for (uint32_t i = 0; i < k; ++i) {

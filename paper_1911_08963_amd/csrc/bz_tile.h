@@ -115,80 +115,184 @@ __device__ __forceinline__ uint32_t colex_digit_s(cptr64 gb, uint32_t i, uint32_
     return lo;
 }
 
-template <int W, int SLOTS, bool PARTIAL, bool STATS>
-__device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
-                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
-                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
-    // ---- locate the rectangle (uniform binary search on tile_begin)
-    uint32_t ri = 0;
-    {
-        uint32_t lo = 0, hi = a.nrects - 1;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (rect_p[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-        }
-        ri = uni(lo);
-    }
-    const uint32_t lane_off = rect_p[ri].lane_off, lane_n = rect_p[ri].lane_n,
-                   lane_t = rect_p[ri].lane_t, head_off = rect_p[ri].head_off,
-                   head_n = rect_p[ri].head_n, head_t = rect_p[ri].head_t;
-    const uint64_t lane_count = rect_p[ri].lane_count, head_count = rect_p[ri].head_count,
-                   head_blocks = rect_p[ri].head_blocks;
-    const uint64_t local = tile - rect_p[ri].tile_begin;
-    const uint64_t lb = local / head_blocks, hb = local - lb * head_blocks;
+// Where a tile sits: its rectangle's two factors and the tile's block
+// coordinates along them (all uniform).
+struct TileGeom {
+    uint32_t lane_off, lane_n, lane_t, head_off, head_n, head_t;
+    uint64_t lane_count, head_count, lb, hb;
+};
 
-    // ---- lane subsets: XOR sums and identity weight
-    uint32_t P[SLOTS][W];
-    uint32_t low[SLOTS];
-    uint32_t pen[SLOTS];
-    uint32_t nvalid = 0;
+__device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_p, uint64_t tile) {
+    uint32_t lo = 0, hi = nrects - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (rect_p[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t ri = uni(lo);
+    TileGeom t;
+    t.lane_off = rect_p[ri].lane_off; t.lane_n = rect_p[ri].lane_n; t.lane_t = rect_p[ri].lane_t;
+    t.head_off = rect_p[ri].head_off; t.head_n = rect_p[ri].head_n; t.head_t = rect_p[ri].head_t;
+    t.lane_count = rect_p[ri].lane_count;
+    t.head_count = rect_p[ri].head_count;
+    const uint64_t head_blocks = rect_p[ri].head_blocks;
+    const uint64_t local = tile - rect_p[ri].tile_begin;
+    t.lb = local / head_blocks;
+    t.hb = local - t.lb * head_blocks;
+    return t;
+}
+
+// The lane subsets of a tile: lane l, slot s holds lane subset
+// lb * 64 * SLOTS + s * 64 + l (colex rank); P[s] is the XOR of its rows, low[s]
+// the number of its rows below k_low, pen[s] = 0x10000 when the rank is past
+// the factor's end. Returns the number of valid lane subsets (uniform).
+// No branch depends on the lane: a lane past the end unranks rank 0 and is
+// masked by pen. (With an "if (valid)" here the optimizer specialised the
+// tile's uniform combination count per divergent path and the wave took the
+// wrong path's value.)
+template <int W, int SLOTS>
+__device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low, const uint32_t *srow,
+                                               const uint64_t *sbin, uint32_t bt, uint32_t lane,
+                                               uint32_t (&P)[SLOTS][W], uint32_t (&low)[SLOTS],
+                                               uint32_t (&pen)[SLOTS]) {
+    const uint64_t base = t.lb * (kWaveSize * SLOTS);
+    const uint32_t nvalid =
+        uni(t.lane_count > base ? (uint32_t)umin64(t.lane_count - base, (uint64_t)kWaveSize * SLOTS) : 0u);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const uint64_t q = (uint64_t)lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize + lane;
-        const bool valid = q < lane_count;
+        const uint64_t q = base + (uint64_t)s * kWaveSize + lane;
+        const bool valid = q < t.lane_count;
+        uint64_t r = valid ? q : 0ull;
 #pragma unroll
         for (int w = 0; w < W; ++w) P[s][w] = 0;
         low[s] = 0;
         pen[s] = valid ? 0u : 0x10000u;
-        if (valid) {
-            uint64_t r = q;
-            uint32_t hi = lane_n - 1;
-            for (uint32_t i = lane_t; i >= 1; --i) {
-                uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
-                r -= sbin[c * bt + i];
-                const uint32_t row = lane_off + c;
+        uint32_t hi = t.lane_n - 1;
+        for (uint32_t i = t.lane_t; i >= 1; --i) {
+            uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
+            r -= sbin[c * bt + i];
+            const uint32_t row = t.lane_off + c;
 #pragma unroll
-                for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
-                low[s] += (row < a.k_low) ? 1u : 0u;
-                hi = c - 1;
-            }
+            for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
+            low[s] += (row < k_low) ? 1u : 0u;
+            hi = c - 1;
         }
-        // the number of valid lane subsets in this tile (uniform)
-        const uint64_t first = (uint64_t)lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize;
-        nvalid += (lane_count > first) ? (uint32_t)umin64(lane_count - first, kWaveSize) : 0u;
     }
+    return nvalid;
+}
 
-    // ---- head range of this tile
-    const uint64_t h0 = (uint64_t)hb * a.heads_per_tile;
-    const uint64_t h1 = umin64(h0 + a.heads_per_tile, head_count);
-    uint64_t remaining = h1 - h0;
-    const uint64_t tile_comb = (uint64_t)nvalid * remaining;
+// Visits the head subsets of colex ranks [h0, h0 + count) of the tile's head
+// factor, in order. visit(H, hl, step) gets the XOR H of the head rows
+// (uniform, in SGPRs), the number hl of head rows below k_low (only when
+// COUNT_LOW) and the step index; it returns true to stop the walk early.
+// The smallest head element runs fastest (H = S2 ^ row[e]); S2, the XOR of
+// the other head rows, changes at a Gosper step of the 64-bit mask. Returns
+// whether the walk was stopped.
+template <int W, bool COUNT_LOW, typename Visit>
+__device__ __forceinline__ bool head_walk(const TileGeom &t, cptr32 rows, cptr64 binom_c, uint32_t k_low,
+                                          uint64_t h0, uint64_t count, Visit &&visit) {
+    if (t.head_t == 0) {
+        uint32_t H[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) H[w] = 0;
+        return visit(H, 0u, 0u);
+    }
+    const uint32_t head_off = t.head_off, head_n = t.head_n;
+    uint64_t head_low_mask = 0;
+    if (COUNT_LOW && k_low > head_off) {
+        const uint32_t nl = k_low - head_off;
+        head_low_mask = nl >= 64 ? ~0ull : ((1ull << nl) - 1);
+    }
+    // unrank h0 into the head mask (uniform; binomials through the scalar cache)
+    uint64_t x = 0;
+    {
+        uint64_t r = h0;
+        uint32_t hi = head_n - 1;
+        for (uint32_t i = t.head_t; i >= 1; --i) {
+            uint32_t c = uni(colex_digit_s(binom_c, i, i - 1, hi, r));
+            r -= binom_c[c * (kBinomT + 1) + i];
+            x |= 1ull << c;
+            hi = c - 1;
+        }
+        x = uni64(x);
+    }
+    uint32_t S2[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) S2[w] = 0;
+    {
+        uint64_t rest = x & (x - 1);
+        while (rest) {
+            uint32_t b = (uint32_t)__builtin_ctzll(rest);
+            rest &= rest - 1;
+            cptr32 rp = rows + (head_off + b) * W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) S2[w] ^= rp[w];
+        }
+    }
+    uint64_t remaining = count;
+    uint32_t step = 0;
+    for (;;) {
+        const uint32_t e1 = (uint32_t)__builtin_ctzll(x);
+        const uint64_t xhi = x & (x - 1);
+        const uint32_t e2 = xhi ? (uint32_t)__builtin_ctzll(xhi) : head_n;
+        const uint32_t len = (uint32_t)umin64((uint64_t)(e2 - e1), remaining);
+        uint32_t hl_base = 0;
+        if (COUNT_LOW) hl_base = (uint32_t)__builtin_popcountll(xhi & head_low_mask);
+        // one row ahead: the device rows carry a zero row after row k-1,
+        // so reading row head_off + e + 1 stays inside the buffer
+        cptr32 rp = rows + (head_off + e1) * W;
+        uint32_t nxt[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) nxt[w] = rp[w];
+        for (uint32_t e = e1; e < e1 + len; ++e) {
+            uint32_t H[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) H[w] = S2[w] ^ nxt[w];
+            rp += W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) nxt[w] = rp[w];
+            uint32_t hl = 0;
+            if (COUNT_LOW) hl = hl_base + (((head_low_mask >> e) & 1ull) ? 1u : 0u);
+            if (visit(H, hl, step)) return true;
+            ++step;
+        }
+        remaining -= len;
+        if (remaining == 0) break;
+        // colex successor of the last subset visited, xhi | bit(e2 - 1) (Gosper's step)
+        const uint64_t xl = xhi | (1ull << (e2 - 1));
+        const uint64_t lowbit = xl & (~xl + 1);
+        const uint64_t rr = xl + lowbit;
+        const uint64_t nx = (((rr ^ xl) >> 2) >> __builtin_ctzll(xl)) | rr;
+        uint64_t diff = xhi ^ (nx & (nx - 1));
+        while (diff) {
+            uint32_t b = (uint32_t)__builtin_ctzll(diff);
+            diff &= diff - 1;
+            cptr32 rp2 = rows + (head_off + b) * W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) S2[w] ^= rp2[w];
+        }
+        x = nx;
+    }
+    return false;
+}
+
+template <int W, int SLOTS, bool PARTIAL, bool STATS>
+__device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
+                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
+                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
+    const TileGeom t = locate_tile(a.nrects, rect_p, tile);
+    uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS];
+    const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, P, low, pen);
+    const uint64_t h0 = t.hb * a.heads_per_tile;
+    const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
+    const uint64_t tile_comb = (uint64_t)nvalid * count;
 
     uint32_t m = 0xffffffffu;                    // full: running minimum of all slots
     uint32_t ms[SLOTS], cs[SLOTS];               // partial or statistics: per slot
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) { ms[s] = 0xffffffffu; cs[s] = 0; }
 
-    // low-row mask of the head side (partial matrix only)
-    uint64_t head_low_mask = 0;
-    if (PARTIAL) {
-        if (a.k_low > head_off) {
-            uint32_t nl = a.k_low - head_off;
-            head_low_mask = nl >= 64 ? ~0ull : ((1ull << nl) - 1);
-        }
-    }
-
-    auto step = [&](const uint32_t (&H)[W], uint32_t hl) {
+    head_walk<W, PARTIAL>(t, rows, binom_c, a.k_low, h0, count,
+                          [&](const uint32_t (&H)[W], uint32_t hl, uint32_t) {
         if (!PARTIAL && !STATS) {
             uint32_t acc[SLOTS];
 #pragma unroll
@@ -215,85 +319,8 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
                 }
             }
         }
-    };
-
-    if (head_t == 0) {
-        uint32_t H[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) H[w] = 0;
-        step(H, 0u);
-    } else {
-        // unrank h0 into the head mask (uniform; binomials through the scalar cache)
-        uint64_t x = 0;
-        {
-            uint64_t r = h0;
-            uint32_t hi = head_n - 1;
-            for (uint32_t i = head_t; i >= 1; --i) {
-                uint32_t c = uni(colex_digit_s(binom_c, i, i - 1, hi, r));
-                r -= binom_c[c * (kBinomT + 1) + i];
-                x |= 1ull << c;
-                hi = c - 1;
-            }
-            x = uni64(x);
-        }
-        uint32_t S2[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) S2[w] = 0;
-        {
-            uint64_t rest = x & (x - 1);
-            while (rest) {
-                uint32_t b = (uint32_t)__builtin_ctzll(rest);
-                rest &= rest - 1;
-                cptr32 rp = rows + (head_off + b) * W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) S2[w] ^= rp[w];
-            }
-        }
-        for (;;) {
-            const uint32_t e1 = (uint32_t)__builtin_ctzll(x);
-            const uint64_t xhi = x & (x - 1);
-            const uint32_t e2 = xhi ? (uint32_t)__builtin_ctzll(xhi) : head_n;
-            const uint32_t len = (uint32_t)umin64((uint64_t)(e2 - e1), remaining);
-            uint32_t hl_base = 0;
-            if (PARTIAL) hl_base = (uint32_t)__builtin_popcountll(xhi & head_low_mask);
-            // one row ahead: the device rows carry a zero row after row k-1,
-            // so reading row head_off + e + 1 stays inside the buffer
-            cptr32 rp = rows + (head_off + e1) * W;
-            uint32_t nxt[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) nxt[w] = rp[w];
-            for (uint32_t e = e1; e < e1 + len; ++e) {
-                uint32_t H[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) H[w] = S2[w] ^ nxt[w];
-                rp += W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) nxt[w] = rp[w];
-                uint32_t hl = 0;
-                if (PARTIAL || STATS) {
-                    hl = hl_base;
-                    if (PARTIAL) hl += ((head_low_mask >> e) & 1ull) ? 1u : 0u;
-                }
-                step(H, hl);
-            }
-            remaining -= len;
-            if (remaining == 0) break;
-            // colex successor of the last subset visited, xhi | bit(e2 - 1) (Gosper's step)
-            const uint64_t xl = xhi | (1ull << (e2 - 1));
-            const uint64_t lowbit = xl & (~xl + 1);
-            const uint64_t rr = xl + lowbit;
-            const uint64_t nx = (((rr ^ xl) >> 2) >> __builtin_ctzll(xl)) | rr;
-            uint64_t diff = xhi ^ (nx & (nx - 1));
-            while (diff) {
-                uint32_t b = (uint32_t)__builtin_ctzll(diff);
-                diff &= diff - 1;
-                cptr32 rp = rows + (head_off + b) * W;
-#pragma unroll
-                for (int w = 0; w < W; ++w) S2[w] ^= rp[w];
-            }
-            x = nx;
-        }
-    }
+        return false;
+    });
 
     // ---- end of tile: weights, wave reduction, atomics
     uint32_t lane_best;
@@ -322,6 +349,59 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
         atomicAdd(a.ncomb, (unsigned long long)tile_comb);
         if (STATS) stats_merge(a.stats, tmin, tcnt);
     }
+}
+
+// Finds one combination of the tile whose weight is target (the tile is
+// known to hold one). The lane subsets are taken one slot at a time (slot s:
+// ranks lb * 64 * SLOTS + s * 64 + lane), each against a walk over the tile's
+// heads; after each head step a ballot tells whether any lane hit. Returns
+// (uniform) true and, in every lane, the lane-subset rank and head rank of the
+// first hit. Few registers: this runs inside the resident serving kernel.
+template <int W, int SLOTS>
+__device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
+                                             const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
+                                             cptr_rect rect_p, uint64_t tile, uint32_t lane, uint32_t target,
+                                             TileGeom &t, uint64_t &q_hit, uint64_t &h_hit) {
+    t = locate_tile(a.nrects, rect_p, tile);
+    const uint64_t h0 = t.hb * a.heads_per_tile;
+    const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
+    bool found = false;
+    for (int s = 0; s < SLOTS && !found; ++s) {
+        const uint64_t base = t.lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize;
+        if (base >= t.lane_count) break;
+        const uint64_t q = base + lane;
+        const bool valid = q < t.lane_count;      // no lane-dependent branch (see lane_setup)
+        uint32_t P[W], low = 0;
+        const uint32_t pen = valid ? 0u : 0x10000u;
+#pragma unroll
+        for (int w = 0; w < W; ++w) P[w] = 0;
+        {
+            uint64_t r = valid ? q : 0ull;
+            uint32_t hi = t.lane_n - 1;
+            for (uint32_t i = t.lane_t; i >= 1; --i) {
+                uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
+                r -= sbin[c * bt + i];
+                const uint32_t row = t.lane_off + c;
+#pragma unroll
+                for (int w = 0; w < W; ++w) P[w] ^= srow[row * W + w];
+                low += (row < a.k_low) ? 1u : 0u;
+                hi = c - 1;
+            }
+        }
+        head_walk<W, true>(t, rows, binom_c, a.k_low, h0, count,
+                           [&](const uint32_t (&H)[W], uint32_t hl, uint32_t step) {
+            uint32_t v = low + hl + pen;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v += __builtin_popcount(H[w] ^ P[w]);
+            const uint64_t ballot = __builtin_amdgcn_ballot_w64(v == target);
+            if (ballot == 0) return false;
+            q_hit = base + (uint64_t)__builtin_ctzll(ballot);
+            h_hit = h0 + step;
+            found = true;
+            return true;
+        });
+    }
+    return found;
 }
 
 }  // namespace bz
