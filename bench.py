@@ -1,6 +1,7 @@
 """Benchmark: row-combinations/s and time-to-d of the Brouwer-Zimmermann search on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain192] [--no-cpu]
+                    [--batch 4096] [--serve-seconds 60]
 
 One step is one complete minimum-distance computation of the workload's code:
 bz_prepare (information sets, Gamma_j, upload), the level loop of Alg. 1 with
@@ -11,7 +12,9 @@ Printed: one JSON line with value = combinations enumerated per second of
 wall time over the timed steps, ms_per_step = time-to-d, the roofline of the
 enumeration kernel (int32 VALU: 2W+1 operations per combination, measured
 with HIP events on the search stream) and the CPU oracle timed on a bounded
-sample of the same code.
+sample of the same code. Beside it: the batched workload in one persistent
+launch against plain per-code launches (codes/s), and a Poisson serving
+stream through the resident server (p50/p99 latency, codes/s).
 """
 from __future__ import annotations
 
@@ -91,6 +94,11 @@ def main():
                     help="codes in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-cap", type=float, default=1e10,
                     help="keep batched-workload codes whose estimated cost is at most this")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson serving stream (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-cap", type=float, default=1e11,
+                    help="serving admission: reject requests whose estimated cost exceeds this")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -183,6 +191,14 @@ def main():
     }
     if args.batch:
         line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap)
+    if args.serve_seconds > 0:
+        from paper_1911_08963_amd import serving
+        sv = serving.run(args.serve_rate, args.serve_seconds, cost_cap=args.serve_cap,
+                         progress=lambda m: print(m, file=sys.stderr, flush=True))
+        sv["workload"] = ("serving: Poisson arrivals (seed 7), request i a random binary code from seed "
+                          "2000000+i with n ~ U{64..192}, k ~ U{ceil(n/3)..floor(n/2)}; requests whose "
+                          "estimated cost exceeds cost_cap are rejected at admission")
+        line["serving"] = sv
     if not args.no_cpu:
         import oracle
         t = time.perf_counter()

@@ -171,6 +171,10 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
     Lo.off_rects = off; off = align256(off + Lo.rects.size() * sizeof(bz::Rect));
     Lo.off_stats = off; off = align256(off + (size_t)Lo.stats_total * sizeof(bz::BatchStat));
     Lo.off_recover = off; off = align256(off + count * sizeof(bz::BatchRecover));
+    // the log is a ring indexed with a mask: a power of two at least the entries possible
+    uint64_t cap2 = 1;
+    while (cap2 < Lo.log_cap) cap2 <<= 1;
+    Lo.log_cap = cap2;
     Lo.off_log = off; off = align256(off + (Lo.log_cap + 3) * sizeof(unsigned long long));
     Lo.off_done = off; off = align256(off + sizeof(uint32_t));
     Lo.total = std::max(off, kWsBytes);

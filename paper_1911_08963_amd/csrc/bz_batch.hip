@@ -38,19 +38,76 @@ namespace bz {
 
 constexpr uint64_t kShareTiles = 8;   // tasks with this many tiles are offered to helpers
 
-// Wave-level atomics without a lane-dependent branch: every lane targets the
-// same word, only lane 0 contributes a value, and the compiler's atomic
-// optimizer folds the wave into one memory operation. Lane 0's return value is
-// the word's old value, which readfirstlane hands to the whole wave.
+// Wave-level atomics: one memory operation per wave, by construction. The
+// asm block (skipped when no lane is active) narrows exec to the wave's
+// first active lane, issues a single
+// global atomic and waits for it before restoring exec; readfirstlane then
+// hands the old value to the whole wave. (Left to the compiler, a wave-wide
+// atomic is folded into one operation only when the optimizer can prove its
+// address uniform; when it cannot, all 64 lanes hit the word and a tile
+// claim costs 64 atomics on the hottest cache line.) The fences give the
+// acquire/release ordering of the operation at agent scope.
 __device__ __forceinline__ unsigned long long wave_fetch_add64(unsigned long long *p, unsigned long long v,
                                                                uint32_t lane) {
-    const unsigned long long mine = lane == 0 ? v : 0ull;
-    unsigned long long old = __hip_atomic_fetch_add(p, mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    (void)lane;
+    unsigned long long old;
+    uint64_t save;
+    uint32_t first;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile(
+        "s_cmp_eq_u64 exec, 0\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        "s_mov_b64 %1, exec\n\t"
+        "s_ff1_i32_b64 %2, exec\n\t"
+        "s_lshl_b64 exec, 1, %2\n\t"
+        "global_atomic_add_x2 %0, %3, %4, off sc0\n\t"
+        "s_waitcnt vmcnt(0)\n\t"
+        "s_mov_b64 exec, %1\n"
+        "1:"
+        : "=&v"(old), "=&s"(save), "=&s"(first)
+        : "v"(p), "v"(v)
+        : "memory", "scc");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return uni64(old);
 }
 
 __device__ __forceinline__ void wave_fetch_max64(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t save;
+    uint32_t first;
+    asm volatile(
+        "s_cmp_eq_u64 exec, 0\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        "s_mov_b64 %0, exec\n\t"
+        "s_ff1_i32_b64 %1, exec\n\t"
+        "s_lshl_b64 exec, 1, %1\n\t"
+        "global_atomic_umax_x2 %2, %3, off\n\t"
+        "s_waitcnt vmcnt(0)\n\t"
+        "s_mov_b64 exec, %0\n"
+        "1:"
+        : "=&s"(save), "=&s"(first)
+        : "v"(p), "v"(v)
+        : "memory", "scc");
+}
+
+// The same, returning the old value (relaxed).
+__device__ __forceinline__ unsigned long long wave_fetch_max64_old(unsigned long long *p, unsigned long long v) {
+    unsigned long long old;
+    uint64_t save;
+    uint32_t first;
+    asm volatile(
+        "s_cmp_eq_u64 exec, 0\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        "s_mov_b64 %1, exec\n\t"
+        "s_ff1_i32_b64 %2, exec\n\t"
+        "s_lshl_b64 exec, 1, %2\n\t"
+        "global_atomic_umax_x2 %0, %3, %4, off sc0\n\t"
+        "s_waitcnt vmcnt(0)\n\t"
+        "s_mov_b64 exec, %1\n"
+        "1:"
+        : "=&v"(old), "=&s"(save), "=&s"(first)
+        : "v"(p), "v"(v)
+        : "memory", "scc");
+    return uni64(old);
 }
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
@@ -126,7 +183,7 @@ __device__ __forceinline__ void log_append(const BatchArgs &b, uint32_t code, ui
     if (tail - head >= b.log_cap) return;          // full: the owner runs the task alone
     const unsigned long long pos = wave_fetch_add64(b.log_tail, 1ull, lane);
     if (lane == 0)
-        __hip_atomic_store(b.log + pos % b.log_cap, (unsigned long long)((((uint64_t)code) << 24) | epoch) + 1ull,
+        __hip_atomic_store(b.log + (pos & (b.log_cap - 1)), (unsigned long long)((((uint64_t)code) << 24) | epoch) + 1ull,
                            __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -333,14 +390,13 @@ __device__ __forceinline__ void serve_view(const ServeArgs &sv, uint32_t lane, u
     const uint64_t now = uni64(wall_clock64());
     const uint64_t last = uni64(__hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (now - last <= kPollTicks || now < last) return;
-    const unsigned long long mine = lane == 0 ? now : 0ull;
-    const uint64_t old = uni64(__hip_atomic_fetch_max(v, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t old = wave_fetch_max64_old(v, now);
     if (now - old <= kPollTicks || now < old) return;     // another wave polls
     // the host raises published before it sets shutdown: read them in the other order
     const uint32_t s = uni(__hip_atomic_load(sv.shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
     const uint64_t p = uni64(__hip_atomic_load(sv.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
-    __hip_atomic_fetch_max(v + 1, lane == 0 ? (unsigned long long)p : 0ull, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wave_fetch_max64(v + 1, p);
     if (s && lane == 0) __hip_atomic_store(v + 2, (unsigned long long)s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (p > pub) pub = p;
     if (s > stop) stop = s;
@@ -353,7 +409,7 @@ __device__ __forceinline__ void serve_view(const ServeArgs &sv, uint32_t lane, u
 template <bool STATS>
 __device__ bool serve_start(const ServeArgs &sv, uint64_t ticket, uint32_t lane) {
     const BatchArgs &b = sv.b;
-    const ServeReq *R = sv.reqs + ticket % sv.ring;
+    const ServeReq *R = sv.reqs + (ticket & (sv.ring - 1));
     const uint32_t slot = (uint32_t)ticket;
     const uint64_t *src = (const uint64_t *)uni64(sys_load64(&R->src));
     uint64_t *dst = (uint64_t *)uni64(sys_load64(&R->dst));
@@ -490,7 +546,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
                 uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
             for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
                 const unsigned long long ent = uni64(
-                    __hip_atomic_load(b.log + q % b.log_cap, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                    __hip_atomic_load(b.log + (q & (b.log_cap - 1)), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
                 if (ent == 0) break;                              // being written
                 const uint32_t cc = (uint32_t)((ent - 1) >> 24);
                 const uint64_t ep = (ent - 1) & ((1ull << 24) - 1);

@@ -112,7 +112,7 @@ struct BatchArgs {
     unsigned long long *next_code;// codes not yet started: next index to hand out
     unsigned int *done_count;
     const uint32_t *cancel;
-    uint64_t log_cap;             // ring size of the log (entry q lives at q % log_cap)
+    uint64_t log_cap;             // ring size of the log, a power of two (entry q at q & (log_cap - 1))
     uint32_t ncodes, _pad[3];
 };
 
@@ -165,7 +165,7 @@ struct ServeArgs {
     ServeRecord *records;         // pinned, one per slot
     BatchStat *host_stats;        // pinned, stats_cap per slot
     unsigned long long *view;     // device: [last poll time, published seen, shutdown seen]
-    uint64_t ring;                // entries of reqs
+    uint64_t ring;                // entries of reqs, a power of two
     uint32_t stats_cap, _pad;
 };
 

@@ -305,7 +305,8 @@ bz_status bz_server_create(const bz_server_opts *o, bz_server **out) {
     s->arena_bytes = opt.arena_bytes ? opt.arena_bytes : ((size_t)1 << 30);
     s->codes_per_launch = opt.codes_per_launch ? opt.codes_per_launch : (1u << 20);
     s->hbm_budget = opt.hbm_budget;
-    s->ring = std::max<uint64_t>(1024, 4ull * s->slots);
+    s->ring = 1024;                          // a power of two, at least 4 x slots
+    while (s->ring < 4ull * s->slots) s->ring <<= 1;
     if (s->arena_bytes < kSlotBytes) return fail(BZ_EINVAL, "arena_bytes below one request");
     BZ_HIP(hipGetDevice(&s->device));
     bz_status st0 = bz::device_const(s->device, s->dc);
@@ -429,7 +430,7 @@ bz_status bz_server_submit(bz_server *s, const bz_code *c, const bz_opts *o, bz_
         if (st != BZ_OK) return st;
         dt = 0;
     }
-    const uint64_t e = dt % s->ring;
+    const uint64_t e = dt & (s->ring - 1);
     if (s->ring_busy[e]) return fail(BZ_EBUSY, "request ring entry still in use");
 
     bz::ServeReq R{};

@@ -146,7 +146,8 @@ __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_
 // the number of its rows below k_low, pen[s] = 0x10000 when the rank is past
 // the factor's end. Returns the number of valid lane subsets (uniform).
 // No branch depends on the lane: a lane past the end unranks rank 0 and is
-// masked by pen. (With an "if (valid)" here the optimizer specialised the
+// masked by pen; only a slot with no valid lane at all is skipped, a uniform
+// test. (With an "if (valid)" per lane here the optimizer specialised the
 // tile's uniform combination count per divergent path and the wave took the
 // wrong path's value.)
 template <int W, int SLOTS>
@@ -159,13 +160,15 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
         uni(t.lane_count > base ? (uint32_t)umin64(t.lane_count - base, (uint64_t)kWaveSize * SLOTS) : 0u);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const uint64_t q = base + (uint64_t)s * kWaveSize + lane;
+        const uint64_t first = base + (uint64_t)s * kWaveSize;
+        const uint64_t q = first + lane;
         const bool valid = q < t.lane_count;
-        uint64_t r = valid ? q : 0ull;
 #pragma unroll
         for (int w = 0; w < W; ++w) P[s][w] = 0;
         low[s] = 0;
         pen[s] = valid ? 0u : 0x10000u;
+        if (first >= t.lane_count) continue;      // uniform: a slot with no valid lane
+        uint64_t r = valid ? q : 0ull;
         uint32_t hi = t.lane_n - 1;
         for (uint32_t i = t.lane_t; i >= 1; --i) {
             uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);

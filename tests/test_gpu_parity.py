@@ -182,3 +182,22 @@ def test_max_level_and_cancel(bz):
                           raise_on_error=False)
     assert got.status == bz.BZ_EINVAL
     code.close()
+
+
+def test_plain192_full_run_matches_oracle(bz):
+    """The whole [192, 64] search in statistics mode against the oracle's full run (d = 35)."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "plain192_oracle.json")))
+    c = inputs.plain_code("plain192")
+    assert c.draws == gold["draws"]
+    code = bz.Code(c.G, c.n)
+    _say("case plain192 full, statistics mode")
+    got = bz.min_distance(code, stats=True)
+    assert got.d == gold["d"] == 35
+    assert (got.lower_bound, got.upper_bound) == (gold["lower_bound"], gold["upper_bound"])
+    assert got.combinations == gold["combinations"]
+    assert [list(s) for s in got.stats] == gold["stats"]
+    _check_witness(got, c.G, c.n)
+    fast = bz.min_distance(code)
+    assert fast.d == 35
+    _check_witness(fast, c.G, c.n)
+    code.close()

@@ -1,0 +1,46 @@
+"""The persistent kernels issue each atomic from one lane (compiled code check, CPU).
+
+Work claims, completions and log appends are wave-wide operations on a few hot
+words. Each must reach memory as one atomic per wave: an atomic executed by
+all 64 lanes multiplies the traffic on those cache lines by 64 (the search
+stays correct but runs several times slower). This compiles the batch/serving
+kernels to gfx950 assembly with hipcc and checks every global atomic of the
+persistent kernels: it must sit in a single-lane region, either a lane-0
+branch (mbcnt election or saveexec) or the explicit exec narrowing of the
+wave-atomic helpers.
+"""
+from __future__ import annotations
+
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1911_08963_amd", "csrc")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC) and not shutil.which("hipcc"), reason="hipcc not installed")
+def test_persistent_kernel_atomics_are_single_lane(tmp_path):
+    out = tmp_path / "bz_batch.s"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "--cuda-device-only", "-S",
+           os.path.join(CSRC, "bz_batch.hip"), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    s = out.read_text()
+    kernels = re.findall(r"^(_ZN2bz\d+bz_(?:batch|serve)_kernel\w+):", s, re.M)
+    assert len(kernels) == 4
+    for k in kernels:
+        body = s[s.index(k + ":"):s.index(".Lfunc_end", s.index(k + ":"))].splitlines()
+        n = 0
+        for i, line in enumerate(body):
+            if "_atomic_" not in line or line.strip().startswith(";"):
+                continue
+            n += 1
+            ctx = " ".join(body[max(0, i - 14):i])
+            assert ("v_mbcnt" in ctx or "s_and_saveexec" in ctx or "s_lshl_b64 exec" in ctx), \
+                f"{k}: atomic without a single-lane region: {line.strip()}"
+        assert n > 0

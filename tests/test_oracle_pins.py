@@ -313,3 +313,29 @@ def test_parallel_oracle_matches_serial():
                 assert b["d"] == a.d
                 assert [s[:4] for s in b["stats"]] == [s[:4] for s in a.stats]
                 assert bf.in_code(b["witness"], G, n)
+
+
+def test_plain192_full_run_golden_is_consistent():
+    """The stored full [192, 64] run (multi-process oracle) against what pins it down:
+    its first 18 tasks equal the single-process oracle's run to level 6, every task
+    enumerated all C(64, g) sums, the witness is a codeword of weight d, and the
+    bound certified after the last task (Sec. 2.1, three full Gamma_j) reaches d."""
+    import json
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    full = json.load(open(os.path.join(here, "plain192_oracle.json")))
+    to6 = json.load(open(os.path.join(here, "plain_oracle.json")))["plain192"]["per_gamma"]
+    c = inputs.plain_code("plain192")
+    assert full["draws"] == c.draws
+    assert full["stats"][:len(to6["stats"])] == to6["stats"]
+    assert all(s[4] == math.comb(64, s[1]) for s in full["stats"])
+    assert full["combinations"] == sum(s[4] for s in full["stats"])
+    w = np.asarray(full["witness"], dtype=np.uint64)
+    assert int(np.bitwise_count(w).sum()) == full["d"] == 35
+    assert bf.in_code(w, c.G, c.n)
+    j, g = full["stats"][-1][:2]
+    m_f = 3
+    assert (j + 1) * (g + 1) + (m_f - j - 1) * g >= full["d"]
+    # one task earlier the certificate was still short of d
+    pj, pg = full["stats"][-2][:2]
+    assert (pj + 1) * (pg + 1) + (m_f - pj - 1) * pg < full["d"]
+    assert min(s[2] for s in full["stats"]) == full["d"]
