@@ -19,6 +19,7 @@ stream through the resident server (p50/p99 latency, codes/s).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 
 import numpy as np
@@ -31,6 +32,23 @@ sys.path.insert(0, ROOT)
 
 # MI355X int32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock)
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# HBM bytes per launch of the enumeration kernel on the [192,64] workload from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads for
+# a plain copy of known size: x2 and x1), valid for the kernel sources whose
+# hash is given; any other build reports traffic as unmeasured.
+ENUM_TRAFFIC = {"sources_sha256_16": "15c1fee89e0209e0", "workload": "plain192",
+                "bytes_per_launch": (6109.08 * 2 + 2902.91) * 1024}
+KERNEL_SOURCES = ("bz_kernels.hip", "bz_tile.h", "bz_kernels.h", "bz_internal.h", "bz_plan.cpp")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1911_08963_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 WORKLOADS = {
     "plain192": "random binary [192,64] rate-1/3 code, G = [I_64 | R1 | R2], R iid Bernoulli(1/2) "
@@ -80,6 +98,43 @@ def batch_comparison(bz, inputs, count: int, cap: float) -> dict:
     }
 
 
+def time_to_d_small(bz, inputs, name: str, runs: int) -> dict:
+    """Median time-to-d of a small plain workload over many runs (prepare and search split)."""
+    c = inputs.plain_code(name)
+    tot, prep, srch, ds = [], [], [], set()
+    for _ in range(runs):
+        t = time.perf_counter()
+        code = bz.Code(c.G, c.n)
+        r = bz.min_distance(code)
+        tot.append(time.perf_counter() - t)
+        prep.append(r.prepare_s)
+        srch.append(r.search_s)
+        ds.add(r.d)
+        code.close()
+    assert len(ds) == 1
+    med = lambda x: float(np.median(x))
+    return {"workload": name, "n": c.n, "k": c.k, "d": ds.pop(), "runs": runs, "median_s": med(tot),
+            "prepare_s": med(prep), "search_s": med(srch)}
+
+
+def cpu_oracle_rate(c, max_level: int, min_seconds: float, pool=None, nprocs: int = 1):
+    """Combinations/s of the oracle on levels 1..max_level of the code, repeated for min_seconds."""
+    import oracle
+    from oracle import parallel
+    t = time.perf_counter()
+    done = reps = 0
+    while reps == 0 or time.perf_counter() - t < min_seconds:
+        if pool is None:
+            ro = oracle.min_distance(c.G, c.n, max_level=max_level)
+            done += ro.combinations
+        else:
+            ro = parallel.min_distance_parallel(c.G, c.n, nprocs=nprocs, max_level=max_level, pool=pool)
+            done += ro["combinations"]
+        reps += 1
+    dt = time.perf_counter() - t
+    return done / dt, done, reps, dt
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +144,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-max-level", type=int, default=6)
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
-                    help="repeat the CPU-oracle sample until this much time has accumulated")
+                    help="repeat each CPU-oracle sample until this much time has accumulated")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="processes of the multi-process oracle (0 = min(16, cpu count))")
+    ap.add_argument("--small-runs", type=int, default=100,
+                    help="runs of the [40,20] and [128,64] workloads for their median time-to-d (0 skips)")
     ap.add_argument("--batch", type=int, default=4096,
                     help="codes in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-cap", type=float, default=1e10,
@@ -108,6 +167,14 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    pool, nprocs = None, 1
+    if not args.no_cpu and not args.copy_ref:
+        # the oracle's worker processes are forked before anything touches the GPU
+        import multiprocessing as mp
+        nprocs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        pool = mp.get_context("fork").Pool(nprocs)
+
     import torch
 
     from paper_1911_08963_amd import inputs
@@ -182,13 +249,32 @@ def main():
             "peak": PEAK_INT32_TOPS,
             "unit": "TOP/s (int32 lane operations)",
             "frac": achieved / PEAK_INT32_TOPS,
-            "traffic": None,
+            "traffic": (ENUM_TRAFFIC["bytes_per_launch"]
+                        if (kernel_sources_hash() == ENUM_TRAFFIC["sources_sha256_16"]
+                            and args.workload == ENUM_TRAFFIC["workload"]) else None),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": 0,
             "kernel": "bz_enum_kernel",
             "ops_per_combination": 2 * W + 1,
             "avg_launch_ms": kern / launches * 1e3,
             "avg_combinations_per_launch": comb / launches,
         },
     }
+    rate = ctypes.c_double()
+    secs = ctypes.c_double()
+    if bz.lib().bz_debug_valu_rate(0, ctypes.byref(rate), ctypes.byref(secs)) == 0:
+        line["roofline"]["measured_peak"] = rate.value / 1e12
+        line["roofline"]["frac_of_measured_peak"] = achieved / (rate.value / 1e12)
+        print(f"measured int32 VALU rate {rate.value / 1e12:.2f} TOP/s ({secs.value * 1e3:.1f} ms probe)",
+              file=sys.stderr, flush=True)
+    line["time_to_d_s"] = {"plain192": {
+        "workload": args.workload, "n": c.n, "k": c.k, "d": d, "runs": args.steps,
+        "median_s": float(np.median([r.prepare_s + r.search_s for r in results])),
+        "prepare_s": float(np.median([r.prepare_s for r in results])),
+        "search_s": float(np.median([r.search_s for r in results]))}}
+    if args.small_runs:
+        for name in ("plain40", "plain128"):
+            line["time_to_d_s"][name] = time_to_d_small(bz, inputs, name, args.small_runs)
     if args.batch:
         line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap)
     if args.serve_seconds > 0:
@@ -200,20 +286,17 @@ def main():
                           "estimated cost exceeds cost_cap are rejected at admission")
         line["serving"] = sv
     if not args.no_cpu:
-        import oracle
-        t = time.perf_counter()
-        done = 0
-        reps = 0
-        while reps == 0 or time.perf_counter() - t < args.cpu_min_seconds:
-            ro = oracle.min_distance(c.G, c.n, max_level=args.cpu_max_level)
-            done += ro.combinations
-            reps += 1
-        dt = time.perf_counter() - t
+        v1, n1, r1, t1 = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds)
+        vp, np_, rp, tp = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds, pool, nprocs)
+        pool.close()
         line["cpu_baseline"] = {
-            "value": done / dt, "unit": "combinations/s", "cores": 1, "kind": "oracle",
-            "sample": f"single-threaded C oracle on the same code, levels 1-{args.cpu_max_level} of "
-                      f"all {ro.num_full} Gamma_j, {reps} repetitions ({done} combinations in "
-                      f"{dt:.1f} s)",
+            "value": vp, "unit": "combinations/s", "cores": nprocs, "kind": "oracle",
+            "sample": f"C oracle on the same code, levels 1-{args.cpu_max_level} of all 3 Gamma_j, "
+                      f"in {nprocs} processes splitting each level's lex prefixes cyclically (Alg. 3); "
+                      f"{rp} repetitions ({np_} combinations in {tp:.1f} s)",
+            "single_core": {"value": v1, "cores": 1,
+                            "sample": f"the same levels single-threaded, {r1} repetitions ({n1} combinations "
+                                      f"in {t1:.1f} s)"},
         }
     print(json.dumps(line), flush=True)
 

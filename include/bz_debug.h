@@ -1,8 +1,9 @@
 /*
- * bz_debug.h -- host-only inspection entry points of libbz.
+ * bz_debug.h -- inspection and measurement entry points of libbz.
  *
- * They run without a GPU: they expose the host halves of bz_prepare and of the
- * level planner so that tests (and curious users) can check them on a CPU.
+ * The first two run without a GPU: they expose the host halves of bz_prepare
+ * and of the level planner so that tests (and curious users) can check them
+ * on a CPU. The last measures the device's sustained integer issue rate.
  * Same conventions as bz.h (status codes, LSB-first uint64 rows, no retained
  * pointers, bz_last_error for details).
  */
@@ -43,6 +44,15 @@ typedef struct {
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                               uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used);
+
+/* Sustained int32 VALU rate of the current device on the enumeration's own
+ * instruction pair (an XOR with a wave-uniform operand, then a popcount that
+ * accumulates), over 8 independent chains per lane in every wave the device
+ * holds. iters: loop trips per lane (0 = 200000). Writes lane operations per
+ * second (2 per XOR+popcount step) and the kernel's device seconds. It is the
+ * measured peak beside the specification's (256 CUs x 4 SIMDs x 16 lanes x
+ * clock). Errors: EINVAL (null output), EDEVICE. */
+bz_status bz_debug_valu_rate(uint32_t iters, double *lane_ops_per_s, double *seconds);
 
 #ifdef __cplusplus
 }

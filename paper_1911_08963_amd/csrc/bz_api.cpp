@@ -708,4 +708,34 @@ bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t h
     return BZ_OK;
 }
 
+bz_status bz_debug_valu_rate(uint32_t iters, double *lane_ops_per_s, double *seconds) {
+    if (!lane_ops_per_s || !seconds) return fail(BZ_EINVAL, "null output");
+    if (iters == 0) iters = 200000;
+    int dev = 0;
+    BZ_HIP(hipGetDevice(&dev));
+    DeviceConst dc;
+    bz_status s0 = device_const(dev, dc);
+    if (s0 != BZ_OK) return s0;
+    const uint32_t blocks = (uint32_t)(dc.cus * bz::valu_probe_blocks_per_cu());
+    uint32_t *sink = nullptr;
+    BZ_HIP(hipMalloc((void **)&sink, (size_t)blocks * bz::kBlock * sizeof(uint32_t)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Guard {
+        uint32_t *p; hipEvent_t &a, &b;
+        ~Guard() { (void)hipFree(p); if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); }
+    } g{sink, e0, e1};
+    BZ_HIP(hipEventCreate(&e0));
+    BZ_HIP(hipEventCreate(&e1));
+    BZ_HIP(bz::launch_valu_probe(iters / 10 + 1, blocks, sink, nullptr));       // warm-up: clocks up
+    BZ_HIP(hipEventRecord(e0, nullptr));
+    BZ_HIP(bz::launch_valu_probe(iters, blocks, sink, nullptr));
+    BZ_HIP(hipEventRecord(e1, nullptr));
+    BZ_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *seconds = ms * 1e-3;
+    *lane_ops_per_s = (double)blocks * bz::kBlock * (double)iters * 16.0 / (*seconds);
+    return BZ_OK;
+}
+
 }  // extern "C"

@@ -184,4 +184,8 @@ hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
 
+// Issue-rate probe: 16 int32 lane operations per lane per trip.
+hipError_t launch_valu_probe(uint32_t iters, uint32_t blocks, uint32_t *sink, hipStream_t st);
+int valu_probe_blocks_per_cu();
+
 }  // namespace bz

@@ -184,4 +184,35 @@ hipError_t launch_recover(const RecoverArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Issue-rate probe: 8 independent XOR+popcount chains per lane, the same
+// instruction pair as the enumeration (v_xor with an SGPR operand, then
+// v_bcnt_u32_b32 accumulating). One store per lane keeps the chains alive.
+__global__ __launch_bounds__(kBlock) void bz_valu_probe_kernel(uint32_t iters, uint32_t s0, uint32_t s1,
+                                                               uint32_t *sink) {
+    uint32_t a[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a[c] = threadIdx.x * 2654435761u + (uint32_t)c * 40503u + blockIdx.x;
+    const uint32_t u0 = uni(s0), u1 = uni(s1);
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[c] = bcnt_acc(a[c] ^ ((c & 1) ? u1 : u0), a[c]);
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x ^= a[c];
+    sink[blockIdx.x * kBlock + threadIdx.x] = x;
+}
+
+hipError_t launch_valu_probe(uint32_t iters, uint32_t blocks, uint32_t *sink, hipStream_t st) {
+    hipLaunchKernelGGL(bz_valu_probe_kernel, dim3(blocks), dim3(kBlock), 0, st, iters, 0x9e3779b9u, 0x7f4a7c15u,
+                       sink);
+    return hipGetLastError();
+}
+
+int valu_probe_blocks_per_cu() {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_valu_probe_kernel, kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 }  // namespace bz
