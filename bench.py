@@ -59,7 +59,7 @@ WORKLOADS = {
 }
 
 
-def batch_comparison(bz, inputs, count: int, cap: float) -> dict:
+def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True) -> dict:
     """codes/s of one bz_min_distance_batch call against bz_min_distance per code."""
     import torch
 
@@ -69,6 +69,11 @@ def batch_comparison(bz, inputs, count: int, cap: float) -> dict:
                                         count, cap)
     objs = [bz.Code(c.G, c.n) for c in kept]
     setup = time.perf_counter() - t
+    tiles = None
+    if autotune:
+        # tiles per task, picked by timing the first 512 codes
+        tiles, _ = bz.autotune_batch(objs[: min(512, len(objs))])
+        print(f"autotune batch: {tiles} tiles per task", file=sys.stderr, flush=True)
     bz.min_distance_batch(objs[: min(64, len(objs))])            # warm-up: code objects, graph path
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -91,7 +96,7 @@ def batch_comparison(bz, inputs, count: int, cap: float) -> dict:
         "workload": "batched: random binary codes, n ~ U{48..160}, rho ~ U[0.33, 0.6], k = round(n rho), "
                     "seeds 1000000+i, kept when the estimated cost is <= cap",
         "codes": len(objs), "drawn": drawn, "cost_cap": cap, "combinations": comb,
-        "batched_s": tb, "plain_s": tp,
+        "batched_s": tb, "plain_s": tp, "tiles_per_task": tiles if tiles else 64,
         "batched_codes_per_s": len(objs) / tb, "plain_codes_per_s": len(objs) / tp,
         "speedup": tp / tb, "batched_combinations_per_s": comb / tb,
         "d_histogram": {str(d): int(n) for d, n in zip(*np.unique([o.d for o in outs], return_counts=True))},
@@ -158,6 +163,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-cap", type=float, default=1e11,
                     help="serving admission: reject requests whose estimated cost exceeds this")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the fixed rules for slots per lane, tile size and tiles per task")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -194,6 +201,15 @@ def main():
         print(json.dumps({"copy_ref_bytes": args.copy_ref, "launches": 3}), flush=True)
         return
     c = inputs.plain_code(args.workload)
+    tuned = None
+    if args.autotune:
+        # the chunk size and lane sums per lane of this shape, picked by timing
+        probe = bz.Code(c.G, c.n)
+        tuned = bz.autotune(probe.W_full, probe.k)
+        probe.close()
+        print(f"autotune W={tuned['W']} k={tuned['k']}: slots {tuned['slots_per_lane']}, tiles per wave "
+              f"{tuned['tiles_per_wave']} ({tuned['comb_per_s']:.3e} comb/s vs {tuned['default_comb_per_s']:.3e} "
+              "with the fixed rule)", file=sys.stderr, flush=True)
 
     def one_step():
         code = bz.Code(c.G, c.n)
@@ -259,6 +275,7 @@ def main():
             "avg_launch_ms": kern / launches * 1e3,
             "avg_combinations_per_launch": comb / launches,
         },
+        "autotune": tuned,
     }
     rate = ctypes.c_double()
     secs = ctypes.c_double()
@@ -276,7 +293,7 @@ def main():
         for name in ("plain40", "plain128"):
             line["time_to_d_s"][name] = time_to_d_small(bz, inputs, name, args.small_runs)
     if args.batch:
-        line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap)
+        line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune)
     if args.serve_seconds > 0:
         from paper_1911_08963_amd import serving
         sv = serving.run(args.serve_rate, args.serve_seconds, cost_cap=args.serve_cap,

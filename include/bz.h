@@ -108,8 +108,10 @@ typedef struct {
     void *workspace;            /* caller device memory, or NULL: the library allocates     */
     size_t workspace_bytes;
     volatile const uint32_t *cancel;   /* host-visible word; nonzero cancels (nullable)      */
-    uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8, 16); 0 = by row width */
-    uint32_t heads_per_tile;    /* head steps per wave tile; 0 = tuned choice                */
+    uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8, 16); 0 = autotuned or by row width */
+    uint32_t heads_per_tile;    /* head steps per wave tile; 0 = autotuned or the planner's choice      */
+    uint32_t tiles_per_task;    /* batch: tiles a task is cut into (about); 0 = autotuned or 64         */
+    uint32_t _reserved;
 } bz_opts;
 
 typedef struct {
@@ -152,6 +154,42 @@ bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
  * to codes[i]. Returns the first per-code error, or BZ_OK. */
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
                                 bz_result *res, bz_status *per_code);
+
+/* ---- Autotuning of the enumeration's free parameters.
+ *
+ * Two parameters change only speed, never a result: the lane sums a lane keeps
+ * (slots per lane: SLOTS x W registers, the unrolling of several left
+ * combinations per fetched right one, Sec. 2.2.1) and the chunk size of a task
+ * (Sec. 3.1), set as tiles per resident wave: the planner sizes each level's
+ * tiles so the level has about that many per wave the device holds.
+ * bz_autotune times the enumeration kernel on a synthetic full-rank task of k
+ * rows and row width W (the level g with about 2e9 sums) for slots 2/4/8/16 x
+ * tiles per wave 2/4/8/16/32/64, and installs the fastest for W: later
+ * bz_min_distance calls use it when slots_per_lane and heads_per_tile are both
+ * 0 (the fixed rule otherwise: slots by W, 16 tiles per wave). The table is
+ * per process and shared by all threads. Errors: EINVAL (W not 1..8, k not
+ * 2..256), ELIMIT, EDEVICE. */
+typedef struct {
+    uint32_t W, k, g;           /* the shape timed                                       */
+    uint32_t slots_per_lane;    /* chosen                                                */
+    uint32_t tiles_per_wave;    /* chosen                                                */
+    uint32_t heads_per_tile;    /* what that gave at the timed level                     */
+    uint64_t combinations;      /* sums per timed launch (C(k, g))                        */
+    double comb_per_s;          /* with the chosen pair                                  */
+    double default_comb_per_s;  /* with the fixed rule                                   */
+} bz_tune_entry;
+
+bz_status bz_autotune(uint32_t W, uint32_t k, bz_tune_entry *out);
+/* The installed entry for W (EINVAL if none). */
+bz_status bz_autotune_get(uint32_t W, bz_tune_entry *out);
+/* Forget every installed choice (plain and batch). */
+void bz_autotune_clear(void);
+/* Times bz_min_distance_batch on these codes (fast mode, no witness) with
+ * 16, 64, 256 and 1024 tiles per task, twice each, and installs the fastest
+ * for later batch calls that leave tiles_per_task at 0. Writes it and its
+ * best wall time. Errors: as bz_min_distance_batch. */
+bz_status bz_autotune_batch(bz_code *const *codes, uint32_t count, const bz_opts *o, uint32_t *tiles_per_task,
+                            double *seconds);
 
 /* ---- Serving: a resident search that admits requests while it runs.
  *

@@ -43,7 +43,15 @@ class Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("max_level", ctypes.c_uint32),
                 ("hip_stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("cancel", P(ctypes.c_uint32)),
-                ("slots_per_lane", ctypes.c_uint32), ("heads_per_tile", ctypes.c_uint32)]
+                ("slots_per_lane", ctypes.c_uint32), ("heads_per_tile", ctypes.c_uint32),
+                ("tiles_per_task", ctypes.c_uint32), ("_reserved", ctypes.c_uint32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_uint32), ("k", ctypes.c_uint32), ("g", ctypes.c_uint32),
+                ("slots_per_lane", ctypes.c_uint32), ("tiles_per_wave", ctypes.c_uint32),
+                ("heads_per_tile", ctypes.c_uint32), ("combinations", ctypes.c_uint64),
+                ("comb_per_s", ctypes.c_double), ("default_comb_per_s", ctypes.c_double)]
 
 
 class LevelStat(ctypes.Structure):
@@ -98,6 +106,11 @@ def _signatures(lib):
         "bz_min_distance_batch": ([P(vp), u32, P(Opts), P(Result), P(ctypes.c_int)], ctypes.c_int),
         "bz_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "bz_last_error": ([], ctypes.c_char_p),
+        "bz_autotune": ([u32, u32, P(TuneEntry)], ctypes.c_int),
+        "bz_autotune_get": ([u32, P(TuneEntry)], ctypes.c_int),
+        "bz_autotune_clear": ([], None),
+        "bz_autotune_batch": ([P(vp), u32, P(Opts), P(u32), P(ctypes.c_double)], ctypes.c_int),
+        "bz_debug_valu_rate": ([u32, P(ctypes.c_double), P(ctypes.c_double)], ctypes.c_int),
         "bz_server_create": ([P(ServerOpts), P(vp)], ctypes.c_int),
         "bz_server_submit": ([vp, vp, P(Opts), P(Result), P(u64)], ctypes.c_int),
         "bz_server_poll": ([vp, P(u64), P(ctypes.c_int), u32, P(u32)], ctypes.c_int),
@@ -223,8 +236,9 @@ def _workspace(device, nbytes):
     return t
 
 
-def _opts(flags, max_level, stream, ws, cancel, slots, heads) -> Opts:
+def _opts(flags, max_level, stream, ws, cancel, slots, heads, tiles=0) -> Opts:
     o = Opts()
+    o.tiles_per_task = tiles
     o.flags = flags
     o.max_level = max_level
     o.hip_stream = stream
@@ -268,7 +282,7 @@ def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
 
 def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, witness: bool = True,
                        max_level: int = 0, stream=None, stats_cap: int = 512, slots_per_lane: int = 0,
-                       heads_per_tile: int = 0, cancel=None):
+                       heads_per_tile: int = 0, tiles_per_task: int = 0, cancel=None):
     """bz_min_distance_batch: returns (list of SearchResult, list of status)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -278,10 +292,10 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
     flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
         (0 if witness else BZ_F_NO_WITNESS)
     nbytes = ctypes.c_size_t()
-    o = _opts(flags, max_level, stream.cuda_stream, None, cancel, slots_per_lane, heads_per_tile)
+    o = _opts(flags, max_level, stream.cuda_stream, None, cancel, slots_per_lane, heads_per_tile, tiles_per_task)
     _check(lib().bz_workspace_bytes(handles, cnt, ctypes.byref(o), ctypes.byref(nbytes)))
     ws = _workspace(dev, nbytes.value)
-    o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
+    o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile, tiles_per_task)
     res = (Result * cnt)()
     wits = np.zeros((cnt, 4), dtype=np.uint64)
     stb = [(LevelStat * stats_cap)() for _ in range(cnt)]
@@ -302,6 +316,45 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
             o_.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
         outs.append(o_)
     return outs, [per[i] for i in range(cnt)]
+
+
+# ---------------------------------------------------------------- autotuning
+
+def _entry(e: TuneEntry) -> dict:
+    return {f: getattr(e, f) for f, _ in TuneEntry._fields_ if not f.startswith("_")}
+
+
+def autotune(W: int, k: int) -> dict:
+    """bz_autotune: times the (slots, tiles per wave) candidates for row width W and installs the fastest."""
+    e = TuneEntry()
+    _check(lib().bz_autotune(W, k, ctypes.byref(e)))
+    return _entry(e)
+
+
+def autotune_get(W: int):
+    e = TuneEntry()
+    return _entry(e) if lib().bz_autotune_get(W, ctypes.byref(e)) == BZ_OK else None
+
+
+def autotune_clear():
+    lib().bz_autotune_clear()
+
+
+def autotune_batch(codes) -> tuple:
+    """bz_autotune_batch on these codes: (tiles per task installed, its best wall seconds)."""
+    cnt = len(codes)
+    handles = (ctypes.c_void_p * cnt)(*[c.handle.value for c in codes])
+    o = _opts(0, 0, None, None, None, 0, 0)
+    t, sec = ctypes.c_uint32(), ctypes.c_double()
+    _check(lib().bz_autotune_batch(handles, cnt, ctypes.byref(o), ctypes.byref(t), ctypes.byref(sec)))
+    return t.value, sec.value
+
+
+def valu_rate(iters: int = 0) -> tuple:
+    """bz_debug_valu_rate: (int32 lane operations per second, probe seconds)."""
+    r, sec = ctypes.c_double(), ctypes.c_double()
+    _check(lib().bz_debug_valu_rate(iters, ctypes.byref(r), ctypes.byref(sec)))
+    return r.value, sec.value
 
 
 # ---------------------------------------------------------------- serving

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "bz_host.h"
@@ -117,7 +118,9 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         auto it = plan_of.find(key);
         if (it != plan_of.end()) return it->second;
         const uint32_t base = (uint32_t)Lo.plans.size();
-        const uint32_t gmax = bz::build_level_plans(k, slots, opt.heads_per_tile, kBatchTargetTiles, kBatchMaxComb,
+        const uint32_t tiles = opt.tiles_per_task ? opt.tiles_per_task
+                               : (bz::tuned_batch_tiles() ? bz::tuned_batch_tiles() : kBatchTargetTiles);
+        const uint32_t gmax = bz::build_level_plans(k, slots, opt.heads_per_tile, tiles, kBatchMaxComb,
                                                     0, Lo.plans, Lo.rects);
         return plan_of[key] = {base, gmax};
     };
@@ -531,7 +534,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         return BZ_OK;
     }
 
-    std::map<std::pair<uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots) -> plan
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots, tiles/wave) -> plan
     const uint64_t resident_waves = (uint64_t)dc.cus * 32;
     bool done = false;
     for (uint32_t g = 1; g <= k && L < U && !done; ++g) {
@@ -540,13 +543,15 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         for (uint32_t j = 0; j < c->nsets && !done; ++j) {
             if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
             const uint32_t W = c->W(j);
-            const uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
+            uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
+            uint32_t per_wave = 16;                         // tiles per resident wave
+            if (!opt.slots_per_lane && !opt.heads_per_tile) (void)bz::tuned_choice(W, slots, per_wave);
             if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
-            auto key = std::make_pair(g, slots);
+            auto key = std::make_tuple(g, slots, per_wave);
             if (!plans.count(key)) {
                 std::string err;
                 bz::LevelPlan p;
-                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, 16 * resident_waves, p, err))
+                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
                     return fail(BZ_ELIMIT, err);
                 if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
                 plans[key] = std::move(p);

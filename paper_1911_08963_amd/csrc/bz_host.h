@@ -31,6 +31,11 @@ uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, 
                            uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
                            std::vector<Rect> &rects);
 
+// The autotuned (slots per lane, tiles per resident wave) for row width W, if any.
+bool tuned_choice(uint32_t W, uint32_t &slots, uint32_t &tiles_per_wave);
+// The autotuned tiles per task of batches (0 = none).
+uint32_t tuned_batch_tiles();
+
 }  // namespace bz
 
 #define BZ_HIP(call)                                                                                        \
