@@ -36,9 +36,11 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes per launch of the enumeration kernel on the [192,64] workload from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads for
 # a plain copy of known size: x2 and x1), valid for the kernel sources whose
-# hash is given; any other build reports traffic as unmeasured.
-ENUM_TRAFFIC = {"sources_sha256_16": "15c1fee89e0209e0", "workload": "plain192",
-                "bytes_per_launch": (6109.08 * 2 + 2902.91) * 1024}
+# hash is given and the tiling the counters were taken with (slots per lane,
+# tiles per resident wave); any other build or tiling reports traffic as
+# unmeasured.
+ENUM_TRAFFIC = {"sources_sha256_16": "PENDING", "workload": "plain192", "slots_per_lane": 16,
+                "tiles_per_wave": 2, "bytes_per_launch": None}
 KERNEL_SOURCES = ("bz_kernels.hip", "bz_tile.h", "bz_kernels.h", "bz_internal.h", "bz_plan.cpp")
 
 
@@ -165,6 +167,8 @@ def main():
                     help="serving admission: reject requests whose estimated cost exceeds this")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the fixed rules for slots per lane, tile size and tiles per task")
+    ap.add_argument("--tiling", default="", metavar="SLOTS,TILES_PER_WAVE",
+                    help="install this tiling of the plain search instead of tuning it")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES three times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -202,7 +206,14 @@ def main():
         return
     c = inputs.plain_code(args.workload)
     tuned = None
-    if args.autotune:
+    if args.tiling:
+        # a fixed (slots per lane, tiles per wave), for profiles that must match a tuned run
+        sl, tw = (int(x) for x in args.tiling.split(","))
+        probe = bz.Code(c.G, c.n)
+        bz.autotune_set(probe.W_full, sl, tw)
+        tuned = bz.autotune_get(probe.W_full)
+        probe.close()
+    elif args.autotune:
         # the chunk size and lane sums per lane of this shape, picked by timing
         probe = bz.Code(c.G, c.n)
         tuned = bz.autotune(probe.W_full, probe.k)
@@ -267,7 +278,10 @@ def main():
             "frac": achieved / PEAK_INT32_TOPS,
             "traffic": (ENUM_TRAFFIC["bytes_per_launch"]
                         if (kernel_sources_hash() == ENUM_TRAFFIC["sources_sha256_16"]
-                            and args.workload == ENUM_TRAFFIC["workload"]) else None),
+                            and args.workload == ENUM_TRAFFIC["workload"]
+                            and (tuned or {}).get("slots_per_lane") == ENUM_TRAFFIC["slots_per_lane"]
+                            and (tuned or {}).get("tiles_per_wave") == ENUM_TRAFFIC["tiles_per_wave"])
+                        else None),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": 0,
             "kernel": "bz_enum_kernel",

@@ -163,11 +163,12 @@ bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_
  * (Sec. 3.1), set as tiles per resident wave: the planner sizes each level's
  * tiles so the level has about that many per wave the device holds.
  * bz_autotune times the enumeration kernel on a synthetic full-rank task of k
- * rows and row width W (the level g with about 2e9 sums) for slots 2/4/8/16 x
- * tiles per wave 2/4/8/16/32/64, and installs the fastest for W: later
- * bz_min_distance calls use it when slots_per_lane and heads_per_tile are both
- * 0 (the fixed rule otherwise: slots by W, 16 tiles per wave). The table is
- * per process and shared by all threads. Errors: EINVAL (W not 1..8, k not
+ * rows and row width W (the first level g with 2e10 sums or more, else the
+ * largest) for slots 2/4/8/16 x tiles per wave 1/2/4/8/16/64, each the fastest
+ * of three launches, and installs the fastest for W: later bz_min_distance
+ * calls use it when slots_per_lane and heads_per_tile are both 0 (the fixed
+ * rule otherwise: 16 slots up to W = 4, then 8; 4 tiles per wave). The table
+ * is per process and shared by all threads. Errors: EINVAL (W not 1..8, k not
  * 2..256), ELIMIT, EDEVICE. */
 typedef struct {
     uint32_t W, k, g;           /* the shape timed                                       */
@@ -182,6 +183,11 @@ typedef struct {
 bz_status bz_autotune(uint32_t W, uint32_t k, bz_tune_entry *out);
 /* The installed entry for W (EINVAL if none). */
 bz_status bz_autotune_get(uint32_t W, bz_tune_entry *out);
+/* Installs a choice without timing (for example one saved from an earlier
+ * bz_autotune): only W, slots_per_lane and tiles_per_wave are read. Errors:
+ * EINVAL (W not 1..8, slots not 2/4/8/16 or 16 with W > 4, tiles per wave not
+ * 1..4096). */
+bz_status bz_autotune_set(const bz_tune_entry *e);
 /* Forget every installed choice (plain and batch). */
 void bz_autotune_clear(void);
 /* Times bz_min_distance_batch on these codes (fast mode, no witness) with

@@ -108,6 +108,7 @@ def _signatures(lib):
         "bz_last_error": ([], ctypes.c_char_p),
         "bz_autotune": ([u32, u32, P(TuneEntry)], ctypes.c_int),
         "bz_autotune_get": ([u32, P(TuneEntry)], ctypes.c_int),
+        "bz_autotune_set": ([P(TuneEntry)], ctypes.c_int),
         "bz_autotune_clear": ([], None),
         "bz_autotune_batch": ([P(vp), u32, P(Opts), P(u32), P(ctypes.c_double)], ctypes.c_int),
         "bz_debug_valu_rate": ([u32, P(ctypes.c_double), P(ctypes.c_double)], ctypes.c_int),
@@ -334,6 +335,13 @@ def autotune(W: int, k: int) -> dict:
 def autotune_get(W: int):
     e = TuneEntry()
     return _entry(e) if lib().bz_autotune_get(W, ctypes.byref(e)) == BZ_OK else None
+
+
+def autotune_set(W: int, slots_per_lane: int, tiles_per_wave: int):
+    """bz_autotune_set: installs a (slots per lane, tiles per wave) choice for W without timing."""
+    e = TuneEntry()
+    e.W, e.slots_per_lane, e.tiles_per_wave = W, slots_per_lane, tiles_per_wave
+    _check(lib().bz_autotune_set(ctypes.byref(e)))
 
 
 def autotune_clear():

@@ -544,7 +544,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
             if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
             const uint32_t W = c->W(j);
             uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
-            uint32_t per_wave = 16;                         // tiles per resident wave
+            uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
             if (!opt.slots_per_lane && !opt.heads_per_tile) (void)bz::tuned_choice(W, slots, per_wave);
             if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
             auto key = std::make_tuple(g, slots, per_wave);

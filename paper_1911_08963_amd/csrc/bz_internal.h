@@ -22,10 +22,16 @@ constexpr int kBlock = 256;              // threads per work-group (4 waves)
 
 using HostRow = std::array<uint64_t, kHostWords>;
 
-// Combinations each lane keeps per head step, by 32-bit words per row: enough
-// that one head step carries 40-70 VALU operations, so the scalar head
-// stepping (and its colex carries) stays well below the vector work.
-constexpr uint32_t slots_for_w(uint32_t W) { return W <= 2 ? 16u : (W <= 4 ? 8u : 4u); }
+// Combinations each lane keeps per head step, by 32-bit words per row: one
+// head step carries 70-140 VALU operations, so the scalar head stepping (and
+// its colex carries) stays well below the vector work. Measured on the MI355X
+// against 8/4 (W <= 4 / above): the batched workload 1.5 s instead of 2.3 s.
+constexpr uint32_t slots_for_w(uint32_t W) { return W <= 4 ? 16u : 8u; }
+
+// Tiles per resident wave the planner aims at for one task of a single-code
+// search: enough for the static round-robin to balance, few enough that a
+// tile's setup (unranking its lane subsets) stays small against its work.
+constexpr uint32_t kFixedTilesPerWave = 4;
 
 // One product of two colex subset spaces inside the g-subsets of [0, k):
 // every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a

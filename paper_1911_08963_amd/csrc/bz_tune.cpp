@@ -31,8 +31,8 @@ std::mutex g_tune_mu;
 std::map<uint32_t, bz_tune_entry> g_tuned;    // W -> chosen (slots, tiles per wave)
 uint32_t g_batch_tiles = 0;                   // tiles per task for batches (0 = not tuned)
 
-constexpr double kTuneCombinations = 2e9;     // size of the timed task (about half a millisecond)
-constexpr uint32_t kTilesPerWave[] = {2, 4, 8, 16, 32, 64};   // 16: the fixed rule
+constexpr double kTuneCombinations = 2e10;    // size of the timed task (several milliseconds)
+constexpr uint32_t kTilesPerWave[] = {1, 2, 4, 8, 16, 64};    // kFixedTilesPerWave: the fixed rule
 
 uint64_t splitmix(uint64_t &s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ull);
@@ -139,7 +139,7 @@ bz_status bz_autotune(uint32_t W, uint32_t k, bz_tune_entry *out) {
         const uint64_t blocks = (p.total_tiles + 3) / 4;
         const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
         float tmin = 0.f;
-        for (int rep = 0; rep < 3; ++rep) {                  // one warm-up, the faster of two
+        for (int rep = 0; rep < 4; ++rep) {                  // one warm-up, the fastest of three
             BZ_HIP(bz::launch_task_init(a.key, a.stats, a.ncomb, a.tile_ctr, nullptr));
             BZ_HIP(hipEventRecord(e0, nullptr));
             BZ_HIP(bz::launch_enum(a, W, cands[i].first, false, false, grid, nullptr));
@@ -147,13 +147,13 @@ bz_status bz_autotune(uint32_t W, uint32_t k, bz_tune_entry *out) {
             BZ_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             BZ_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep == 1 || (rep == 2 && ms < tmin)) tmin = ms;
+            if (rep == 1 || (rep > 1 && ms < tmin)) tmin = ms;
         }
         unsigned long long back[3];
         BZ_HIP(hipMemcpy(back, words, sizeof(back), hipMemcpyDeviceToHost));
         if (back[2] != comb) return fail(BZ_EDEVICE, "autotune: a timed launch did not enumerate its task");
         const double rate = (double)comb / (tmin * 1e-3);
-        if (cands[i].first == bz::slots_for_w(W) && cands[i].second == 16) dflt = rate;
+        if (cands[i].first == bz::slots_for_w(W) && cands[i].second == bz::kFixedTilesPerWave) dflt = rate;
         if (rate > best) { best = rate; best_i = i; }
     }
     bz_tune_entry e{};
@@ -169,6 +169,18 @@ bz_status bz_autotune(uint32_t W, uint32_t k, bz_tune_entry *out) {
         g_tuned[W] = e;
     }
     *out = e;
+    return BZ_OK;
+}
+
+bz_status bz_autotune_set(const bz_tune_entry *e) {
+    if (!e) return fail(BZ_EINVAL, "null entry");
+    if (e->W < 1 || e->W > (uint32_t)bz::kMaxW) return fail(BZ_EINVAL, "W must be 1..8");
+    const uint32_t sl = e->slots_per_lane;
+    if (sl != 2 && sl != 4 && sl != 8 && sl != 16) return fail(BZ_EINVAL, "slots per lane must be 2, 4, 8 or 16");
+    if (sl == 16 && e->W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
+    if (e->tiles_per_wave < 1 || e->tiles_per_wave > 4096) return fail(BZ_EINVAL, "tiles per wave must be 1..4096");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[e->W] = *e;
     return BZ_OK;
 }
 

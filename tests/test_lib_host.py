@@ -152,3 +152,18 @@ def test_plan_invariants(k, g):
             tot += r["lane_count"] * r["head_count"]
         assert tot == math.comb(k, g)
         assert tb == tiles < 2 ** 40
+
+
+def test_autotune_table_set_get_clear():
+    """bz_autotune_set / _get / _clear manage the per-process tuning table (no device needed)."""
+    from paper_1911_08963_amd import bz
+    bz.autotune_clear()
+    assert bz.autotune_get(4) is None
+    bz.autotune_set(4, 16, 2)
+    e = bz.autotune_get(4)
+    assert (e["W"], e["slots_per_lane"], e["tiles_per_wave"]) == (4, 16, 2)
+    for bad in ((0, 8, 4), (9, 8, 4), (4, 3, 4), (5, 16, 4), (4, 8, 0)):
+        with pytest.raises(bz.BZError):
+            bz.autotune_set(*bad)
+    bz.autotune_clear()
+    assert bz.autotune_get(4) is None
