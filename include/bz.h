@@ -51,9 +51,17 @@ typedef enum {
 
 typedef struct bz_code bz_code;   /* opaque; immutable after bz_prepare */
 
-/* Column-permutation search used to find the information sets (Sec. 2.2,
- * the paragraph on computing the Gamma matrices). perm_trials = 0 or 1
- * scans the columns in their natural order. */
+/* Column-permutation search for the information sets (Sec. 2.2 tries random
+ * permutations of the columns). perm_trials = 0 or 1 scans the columns in
+ * their natural order. With perm_trials = T > 1 the greedy scan runs for
+ * trials t = 0..T-1 over the column order p_t and keeps the trial with the
+ * most full-rank sets, then the largest leftover rank (the first on ties).
+ * p_0 is the natural order; for t >= 1, p_t is the Fisher-Yates shuffle of
+ * (0..n-1) that, for i = n-1 down to 1, swaps positions i and x mod (i+1),
+ * x the next output of SplitMix64 (Steele, Lea, Flood 2014) started from
+ * state perm_seed + t. The sets are sorted ascending, so Gamma_j depends only
+ * on its set. d never depends on the sets; the per-level statistics do.
+ * perm_trials above 100000 is EINVAL. */
 typedef struct {
     uint32_t perm_trials;
     uint32_t flags;             /* BZ_PREPARE_HOST_ONLY: keep Gamma_j on the host only */

@@ -72,6 +72,12 @@ def _load():
         lib.or_lex_sequence.argtypes = [ctypes.c_uint32, ctypes.c_uint32, P(ctypes.c_int32),
                                         ctypes.c_uint64]
         lib.or_lex_sequence.restype = ctypes.c_int64
+        lib.or_set_permutation_search.argtypes = [ctypes.c_uint32, ctypes.c_uint64]
+        lib.or_set_permutation_search.restype = None
+        lib.or_splitmix64.argtypes = [P(ctypes.c_uint64)]
+        lib.or_splitmix64.restype = ctypes.c_uint64
+        lib.or_trial_order.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, P(ctypes.c_int32)]
+        lib.or_trial_order.restype = None
         lib.or_binomial.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         lib.or_binomial.restype = ctypes.c_uint64
         for f in (lib.or_certified_bound, lib.or_level_bound):
@@ -103,17 +109,32 @@ class OracleResult:
     stats: list = field(default_factory=list)   # (matrix, level, min_weight, count_at_min, combinations)
 
 
+class _Permutations:
+    """Sets the permutation search of step 7 for one call (Sec. 2.2's random permutations)."""
+
+    def __init__(self, trials: int, seed: int):
+        self.trials, self.seed = trials, seed
+
+    def __enter__(self):
+        _load().or_set_permutation_search(self.trials, self.seed)
+
+    def __exit__(self, *exc):
+        _load().or_set_permutation_search(0, 0)
+
+
 def min_distance(G: np.ndarray, n: int, *, level_stop: bool = False, max_level: int = 0,
-                 stats_cap: int = 4096) -> OracleResult:
-    """Brouwer-Zimmermann minimum weight (Alg. 1 with the per-Gamma check of Sec. 2.2)."""
+                 stats_cap: int = 4096, perm_trials: int = 0, perm_seed: int = 0) -> OracleResult:
+    """Brouwer-Zimmermann minimum weight (Alg. 1 with the per-Gamma check of Sec. 2.2);
+    perm_trials > 1 searches column permutations for the information sets (Sec. 2.2)."""
     lib = _load()
     G = _as_words(G)
     k, ld = G.shape
     res = _Result()
     stats = (_Stat * stats_cap)()
-    st = lib.or_min_distance(G.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k, n, ld,
-                             OR_LEVEL_STOP if level_stop else 0, max_level, ctypes.byref(res),
-                             stats, stats_cap)
+    with _Permutations(perm_trials, perm_seed):
+        st = lib.or_min_distance(G.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k, n, ld,
+                                 OR_LEVEL_STOP if level_stop else 0, max_level, ctypes.byref(res),
+                                 stats, stats_cap)
     out = OracleResult(int(st), res.d, res.lower_bound, res.upper_bound, res.last_level,
                        res.num_full, res.partial_rank, res.combinations,
                        np.array(list(res.witness), dtype=np.uint64))
@@ -123,9 +144,9 @@ def min_distance(G: np.ndarray, n: int, *, level_stop: bool = False, max_level: 
     return out
 
 
-def prepare(G: np.ndarray, n: int):
-    """Information sets and Gamma matrices (Sec. 2.1). Returns
-    (set_of_column[n], m_f, k_m, gamma[(m_f + [k_m>0]) * k, ld])."""
+def prepare(G: np.ndarray, n: int, perm_trials: int = 0, perm_seed: int = 0):
+    """Information sets and Gamma matrices (Sec. 2.1; Sec. 2.2's permutation search when
+    perm_trials > 1). Returns (set_of_column[n], m_f, k_m, gamma[(m_f + [k_m>0]) * k, ld])."""
     lib = _load()
     G = _as_words(G)
     k, ld = G.shape
@@ -135,14 +156,28 @@ def prepare(G: np.ndarray, n: int):
     cap = (n + 1) * k
     out_ld = (n + 63) // 64
     gam = np.zeros((cap, out_ld), dtype=np.uint64)
-    st = lib.or_prepare(G.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k, n, ld,
-                        soc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(mf),
-                        ctypes.byref(km), gam.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                        out_ld, cap)
+    with _Permutations(perm_trials, perm_seed):
+        st = lib.or_prepare(G.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k, n, ld,
+                            soc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(mf),
+                            ctypes.byref(km), gam.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                            out_ld, cap)
     if st != OR_OK:
         raise ValueError(f"oracle prepare failed with status {st}")
     nsets = mf.value + (1 if km.value > 0 else 0)
     return soc, mf.value, km.value, gam[: nsets * k].copy()
+
+
+def splitmix64(state: int, count: int) -> list:
+    """The first outputs of SplitMix64 from a state (the generator of step 7)."""
+    st = ctypes.c_uint64(state)
+    return [int(_load().or_splitmix64(ctypes.byref(st))) for _ in range(count)]
+
+
+def trial_order(n: int, t: int, seed: int) -> list:
+    """The column scan order p_t of trial t of the permutation search (step 7)."""
+    out = np.zeros(n, dtype=np.int32)
+    _load().or_trial_order(n, t, seed, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return [int(x) for x in out]
 
 
 def lex_sequence(k: int, g: int) -> list:

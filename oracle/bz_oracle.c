@@ -45,8 +45,20 @@
  *      weight of any codeword; the first codeword met with weight < U, or = U
  *      while no witness is held yet, becomes the witness.
  *
+ *   7. Random column permutations (Sec. 2.2: the implementation tries random
+ *      permutations of the columns to find good information sets): with
+ *      or_set_permutation_search(T, seed), step 1 is run T times, trial t
+ *      scanning the columns in the order p_t instead of ascending order, and
+ *      the trial with the most full sets, then the largest k_m, is kept (the
+ *      first such trial on ties). p_0 is the identity; for t >= 1, p_t is a
+ *      Fisher-Yates shuffle of (0..n-1): for i = n-1 down to 1, swap entries i
+ *      and (x mod (i+1)), x the next output of SplitMix64 (Steele, Lea, Flood,
+ *      OOPSLA 2014) started from state seed + t. The sets are sorted ascending
+ *      before step 2, so each Gamma_j depends only on its set.
+ *
  * Readings of the paper that this file takes (the paper is silent on them):
- * the canonical greedy choice of information sets (no random permutations);
+ * the canonical greedy choice of information sets (trial 0 above; the
+ * permutation search only when asked, with the generator above);
  * the reduced echelon basis for every Gamma_j; the per-Gamma bound above; the
  * partial Gamma_m enumerated at every level; k = n returns d = 1 at once (the
  * loop condition fails before any level, since U = n - k + 1 = 1).
@@ -141,38 +153,78 @@ typedef struct {
 
 static void free_code(or_code *oc) { free(oc->gamma); oc->gamma = NULL; }
 
-/* Steps 1 and 2 of the header. */
-static int prepare(const uint64_t *G, int k, int n, int ldw, or_code *oc)
+/* Step 7 of the header: the permutation search's parameters (0 = natural order). */
+static uint32_t g_perm_trials = 0;
+static uint64_t g_perm_seed = 0;
+
+void or_set_permutation_search(uint32_t trials, uint64_t seed)
 {
-    if (!G || k <= 0 || n <= 0 || k > n || n > OR_MAXN || ldw < (n + 63) / 64) return OR_EINVAL;
-    memset(oc, 0, sizeof(*oc));
-    oc->n = n; oc->k = k;
-    row_t *M = (row_t *)malloc(sizeof(row_t) * (size_t)k);
-    int *avail = (int *)malloc(sizeof(int) * (size_t)n);
-    int *piv = (int *)malloc(sizeof(int) * (size_t)n);
-    int sets[OR_MAXM][OR_MAXK];
-    int setsize[OR_MAXM];
-    if (!M || !avail || !piv) { free(M); free(avail); free(piv); return OR_ENOMEM; }
-    for (int c = 0; c < n; ++c) { avail[c] = c; oc->set_of_column[c] = -1; }
-    int navail = n, nsets = 0, status = OR_OK;
+    g_perm_trials = trials;
+    g_perm_seed = seed;
+}
+
+/* SplitMix64: the state advances by the golden gamma; the output mixes it. */
+static uint64_t splitmix64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+uint64_t or_splitmix64(uint64_t *state) { return splitmix64_next(state); }
+
+/* p_t of step 7. */
+static void trial_order(int n, uint32_t t, uint64_t seed, int *order)
+{
+    for (int c = 0; c < n; ++c) order[c] = c;
+    if (t == 0) return;
+    uint64_t st = seed + t;
+    for (int i = n - 1; i >= 1; --i) {
+        int j = (int)(splitmix64_next(&st) % (uint64_t)(i + 1));
+        int tmp = order[i]; order[i] = order[j]; order[j] = tmp;
+    }
+}
+
+void or_trial_order(uint32_t n, uint32_t t, uint64_t seed, int32_t *order)
+{
+    int buf[OR_MAXN];
+    if (n > OR_MAXN) return;
+    trial_order((int)n, t, seed, buf);
+    for (uint32_t c = 0; c < n; ++c) order[c] = buf[c];
+}
+
+static int cmp_int(const void *a, const void *b) { return *(const int *)a - *(const int *)b; }
+
+/* Step 1 with the columns scanned in the given order: fills sets (each sorted
+ * ascending), their sizes, m_f and k_m; returns the number of sets or an error. */
+static int find_sets(const uint64_t *G, int k, int n, int ldw, const int *scan, row_t *M, int *piv,
+                     int sets[][OR_MAXK], int *setsize, int *m_f, int *k_m)
+{
+    int avail[OR_MAXN];
+    for (int c = 0; c < n; ++c) avail[c] = scan[c];
+    int navail = n, nsets = 0;
+    *m_f = 0; *k_m = 0;
     for (;;) {
         load_rows(M, G, k, n, ldw);
         int rank = gauss_jordan(M, k, avail, navail, piv);
-        if (nsets == 0 && rank < k) { status = OR_ERANK; break; }
+        if (nsets == 0 && rank < k) return OR_ERANK;
         if (rank < k) {                       /* the leftover columns          */
-            oc->k_m = rank;
+            *k_m = rank;
             if (rank > 0) {
                 memcpy(sets[nsets], piv, sizeof(int) * (size_t)rank);
+                qsort(sets[nsets], (size_t)rank, sizeof(int), cmp_int);
                 setsize[nsets] = rank;
                 nsets++;
             }
             break;
         }
-        memcpy(sets[nsets], piv, sizeof(int) * (size_t)k);  /* ascending already */
+        memcpy(sets[nsets], piv, sizeof(int) * (size_t)k);
+        qsort(sets[nsets], (size_t)k, sizeof(int), cmp_int);
         setsize[nsets] = k;
         nsets++;
-        oc->m_f++;
-        /* remove the chosen columns from the available list */
+        (*m_f)++;
+        /* remove the chosen columns from the available list, keeping its order */
         int w = 0;
         for (int t = 0; t < navail; ++t) {
             int used = 0;
@@ -180,7 +232,38 @@ static int prepare(const uint64_t *G, int k, int n, int ldw, or_code *oc)
             if (!used) avail[w++] = avail[t];
         }
         navail = w;
-        if (navail == 0) { oc->k_m = 0; break; }
+        if (navail == 0) { *k_m = 0; break; }
+    }
+    return nsets;
+}
+
+/* Steps 1, 2 and 7 of the header. */
+static int prepare(const uint64_t *G, int k, int n, int ldw, or_code *oc)
+{
+    if (!G || k <= 0 || n <= 0 || k > n || n > OR_MAXN || ldw < (n + 63) / 64) return OR_EINVAL;
+    memset(oc, 0, sizeof(*oc));
+    oc->n = n; oc->k = k;
+    row_t *M = (row_t *)malloc(sizeof(row_t) * (size_t)k);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)n);
+    static int sets[OR_MAXM][OR_MAXK], trial_sets[OR_MAXM][OR_MAXK];
+    int setsize[OR_MAXM], trial_size[OR_MAXM];
+    int scan[OR_MAXN];
+    if (!M || !piv) { free(M); free(piv); return OR_ENOMEM; }
+    for (int c = 0; c < n; ++c) oc->set_of_column[c] = -1;
+    int status = OR_OK, nsets = -1;
+    const uint32_t trials = g_perm_trials > 1 ? g_perm_trials : 1;
+    for (uint32_t t = 0; t < trials; ++t) {
+        trial_order(n, t, g_perm_seed, scan);
+        int mf = 0, km = 0;
+        int ns = find_sets(G, k, n, ldw, scan, M, piv, trial_sets, trial_size, &mf, &km);
+        if (ns < 0) { status = ns; break; }   /* rank(G) < k in every order   */
+        if (nsets < 0 || mf > oc->m_f || (mf == oc->m_f && km > oc->k_m)) {
+            nsets = ns; oc->m_f = mf; oc->k_m = km;
+            for (int j = 0; j < ns; ++j) {
+                setsize[j] = trial_size[j];
+                memcpy(sets[j], trial_sets[j], sizeof(int) * (size_t)trial_size[j]);
+            }
+        }
     }
     if (status == OR_OK) {
         oc->nsets = nsets;
@@ -202,7 +285,7 @@ static int prepare(const uint64_t *G, int k, int n, int ldw, or_code *oc)
         }
         free(order);
     }
-    free(M); free(avail); free(piv);
+    free(M); free(piv);
     if (status != OR_OK) free_code(oc);
     return status;
 }

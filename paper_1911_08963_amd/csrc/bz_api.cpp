@@ -387,8 +387,16 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
     std::string err;
     bz_status st = bz::prepare_host(G, k, n, ld_words, opts, *c, err);
     if (st != BZ_OK) return fail(st, err);
-    BZ_HIP(hipGetDevice(&c->device));
     const bool host_only = opts && (opts->flags & BZ_PREPARE_HOST_ONLY);
+    if (host_only) {
+        // no device needed: a server copies Gamma_j from the host copy
+        if (hipGetDevice(&c->device) != hipSuccess) {
+            (void)hipGetLastError();
+            c->device = -1;
+        }
+    } else {
+        BZ_HIP(hipGetDevice(&c->device));
+    }
     // device layout: per matrix (k + 1) x W dwords (the last row zero), then
     // the full rows at a 256-byte boundary
     std::vector<uint32_t> dev_packed;

@@ -9,6 +9,14 @@
 // greedy (first) basis. This is repeated on the remaining columns while they
 // still have rank k.
 //
+// Sec. 2.2 tries random column permutations to find better sets. With
+// perm_trials > 1 the scan above runs once per trial t, over the columns in
+// the order p_t: p_0 is the identity, and for t >= 1 p_t is a Fisher-Yates
+// shuffle (for i = n-1 down to 1, swap positions i and x mod (i+1)) driven by
+// SplitMix64 (Steele, Lea, Flood 2014) from state perm_seed + t. The trial
+// with the most full-rank sets, then the largest leftover rank, wins (the
+// first on ties); each set is then sorted ascending.
+//
 // Gamma_j is G brought to reduced echelon form with S_j's columns taken as
 // pivots first (in ascending order), then the other columns ascending. For a
 // full-rank S_j this puts I_k on S_j. For the leftover set it gives the block
@@ -67,6 +75,54 @@ uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order) 
     return r;
 }
 
+// SplitMix64: advance the state by the golden gamma, then mix.
+uint64_t splitmix64(uint64_t &state) {
+    uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+std::vector<uint32_t> scan_order(uint32_t n, uint32_t trial, uint64_t seed) {
+    std::vector<uint32_t> p(n);
+    for (uint32_t c = 0; c < n; ++c) p[c] = c;
+    if (trial == 0) return p;
+    uint64_t st = seed + trial;
+    for (uint32_t i = n - 1; i >= 1; --i) std::swap(p[i], p[splitmix64(st) % (uint64_t)(i + 1)]);
+    return p;
+}
+
+// Greedy disjoint information sets, scanning the columns in `scan`.
+struct SetChoice {
+    std::vector<std::vector<uint32_t>> sets;
+    uint32_t num_full = 0, partial = 0;
+};
+
+SetChoice find_sets(const std::vector<ColVec> &col, uint32_t k, const std::vector<uint32_t> &scan) {
+    const uint32_t n = (uint32_t)col.size();
+    SetChoice r;
+    std::vector<char> taken(n, 0);
+    for (;;) {
+        XorBasis basis(k);
+        std::vector<uint32_t> S;
+        for (uint32_t t = 0; t < n && S.size() < k; ++t) {
+            const uint32_t cc = scan[t];
+            if (!taken[cc] && basis.insert(col[cc])) S.push_back(cc);
+        }
+        std::sort(S.begin(), S.end());
+        if (S.size() == k) {
+            for (uint32_t cc : S) taken[cc] = 1;
+            r.sets.push_back(S);
+            ++r.num_full;
+            continue;
+        }
+        r.partial = (uint32_t)S.size();
+        if (r.partial) r.sets.push_back(S);
+        break;
+    }
+    return r;
+}
+
 }  // namespace
 
 uint64_t binom_sat(uint32_t a, uint32_t b) {
@@ -85,7 +141,7 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
     if (!G) { err = "G is null"; return BZ_EINVAL; }
     if (k == 0 || k > n || n > (uint32_t)kMaxN) { err = "need 0 < k <= n <= BZ_MAX_N"; return BZ_EINVAL; }
     if (ld < (n + 63) / 64) { err = "ld_words < ceil(n/64)"; return BZ_EINVAL; }
-    if (opts && opts->perm_trials > 1) { err = "column-permutation search is not implemented"; return BZ_EINVAL; }
+    if (opts && opts->perm_trials > 100000) { err = "perm_trials above 100000"; return BZ_EINVAL; }
     if (opts && (opts->flags & ~(uint32_t)BZ_PREPARE_HOST_ONLY)) { err = "unknown prepare flag"; return BZ_EINVAL; }
 
     std::vector<HostRow> rows(k);
@@ -101,25 +157,17 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
         for (uint32_t i = 0; i < k; ++i)
             if (bit(rows[i], cc)) col[cc][i >> 6] |= 1ull << (i & 63);
     }
-    std::vector<char> taken(n, 0);
-    std::vector<std::vector<uint32_t>> sets;
-    uint32_t num_full = 0, partial = 0;
-    for (;;) {
-        XorBasis basis(k);
-        std::vector<uint32_t> S;
-        for (uint32_t cc = 0; cc < n && S.size() < k; ++cc)
-            if (!taken[cc] && basis.insert(col[cc])) S.push_back(cc);
-        if (sets.empty() && S.size() < k) { err = "rank(G) < k"; return BZ_ERANK; }
-        if (S.size() == k) {
-            for (uint32_t cc : S) taken[cc] = 1;
-            sets.push_back(S);
-            ++num_full;
-            continue;
-        }
-        partial = (uint32_t)S.size();
-        if (partial) sets.push_back(S);
-        break;
+    const uint32_t trials = (opts && opts->perm_trials > 1) ? opts->perm_trials : 1;
+    const uint64_t seed = opts ? opts->perm_seed : 0;
+    SetChoice best = find_sets(col, k, scan_order(n, 0, seed));
+    if (best.num_full == 0) { err = "rank(G) < k"; return BZ_ERANK; }
+    for (uint32_t t = 1; t < trials; ++t) {
+        SetChoice s2 = find_sets(col, k, scan_order(n, t, seed));
+        if (s2.num_full > best.num_full || (s2.num_full == best.num_full && s2.partial > best.partial))
+            best = std::move(s2);
     }
+    const std::vector<std::vector<uint32_t>> &sets = best.sets;
+    const uint32_t num_full = best.num_full, partial = best.partial;
 
     c.n = n; c.k = k; c.num_full = num_full; c.partial_rank = partial;
     c.nsets = (uint32_t)sets.size();

@@ -396,7 +396,7 @@ bz_status bz_server_submit(bz_server *s, const bz_code *c, const bz_opts *o, bz_
     if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
     if (((opt.flags & BZ_F_STATS) != 0) != s->stats)
         return fail(BZ_EINVAL, "BZ_F_STATS must match the server's mode");
-    if (c->device != s->device) return fail(BZ_EINVAL, "code prepared on another device");
+    if (c->dev && c->device != s->device) return fail(BZ_EINVAL, "code prepared on another device");
     const size_t payload = c->dev_bytes;
     if (payload > kSlotBytes) return fail(BZ_EINVAL, "code too large for a request slot");
     res->d = 0; res->lower_bound = 0; res->upper_bound = 0; res->last_level = 0;

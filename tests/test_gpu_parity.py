@@ -201,3 +201,40 @@ def test_plain192_full_run_matches_oracle(bz):
     assert fast.d == 35
     _check_witness(fast, c.G, c.n)
     code.close()
+
+
+def test_permutation_search_parity(bz):
+    """Information sets from the column-permutation search: the GPU's statistics equal the
+    oracle's with the same trials and seed; d is the natural-order d."""
+    rng = np.random.default_rng(404)
+    items = []
+    for t in range(8):
+        n = int(rng.integers(20, 70))
+        k = int(rng.integers(6, 18))
+        items.append((_rand(rng, n, k, systematic=bool(t % 2)), n))
+    for name in ("rm17", "rm26"):
+        G, n, k, d = codes.reed_muller(1, 7) if name == "rm17" else codes.reed_muller(2, 6)
+        items.append((G, n))
+    for i, (G, n) in enumerate(items):
+        natural = oracle.min_distance(G, n)
+        for trials, seed in ((12, i), (60, 1000 + i)):
+            _say("case perm", i, "n", n, "k", G.shape[0], "trials", trials)
+            ref = oracle.min_distance(G, n, perm_trials=trials, perm_seed=seed)
+            code = bz.Code(G, n, perm_trials=trials, perm_seed=seed)
+            assert (code.num_full, code.partial_rank) == (ref.num_full, ref.partial_rank)
+            got = bz.min_distance(code, stats=True, raise_on_error=False)
+            assert got.status == ref.status == 0
+            assert got.d == ref.d == natural.d
+            assert [tuple(s) for s in got.stats] == [tuple(s) for s in ref.stats]
+            _check_witness(got, G, n)
+            code.close()
+    # the same permuted codes through the batched search
+    objs = [bz.Code(G, n, perm_trials=60, perm_seed=1000 + i) for i, (G, n) in enumerate(items)]
+    outs, sts = bz.min_distance_batch(objs, stats=True)
+    for i, ((G, n), got, st) in enumerate(zip(items, outs, sts)):
+        ref = oracle.min_distance(G, n, perm_trials=60, perm_seed=1000 + i)
+        assert st == 0 and got.d == ref.d
+        assert [tuple(s) for s in got.stats] == [tuple(s) for s in ref.stats]
+        _check_witness(got, G, n)
+    for o in objs:
+        o.close()
