@@ -163,6 +163,31 @@ bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
                                 bz_result *res, bz_status *per_code);
 
+/* ---- Codewords of a given weight (the exact count A_w; not in the paper,
+ * which returns d only).
+ *
+ * Runs the tasks (Gamma_j, g) in the order of Alg. 1, collects every sum of
+ * weight w, and stops once the bound certified by the completed tasks (the
+ * per-Gamma bound of Sec. 2.2 / Alg. 1) exceeds w: then every codeword not
+ * enumerated weighs more than w. A codeword is met in every Gamma_j in which
+ * it is light, so the library keeps the distinct codewords. */
+typedef struct {
+    uint32_t weight;            /* in: w; 0 = the minimum distance (found first). out: w     */
+    uint32_t last_level;        /* last level g enumerated                                   */
+    uint64_t count;             /* codewords of weight w                                     */
+    uint64_t hits;              /* weight-w sums met (with repeats across the Gamma_j)        */
+    uint64_t combinations;      /* sums enumerated by the counting pass                      */
+    uint64_t *codewords;        /* caller buffer of codewords_cap x ceil(n/64) words, or NULL */
+    uint64_t codewords_cap;
+    uint64_t codewords_len;     /* codewords written: the smallest as integers (last word most significant) */
+    double search_s;
+} bz_weight_count;
+
+/* o: hip_stream; max_level (0 = none; ELIMIT if reached before the count is
+ * complete). Errors: EINVAL (null, host-only code), ELIMIT (C(k,g) >= 2^63,
+ * max_level, or more than 2^21 weight-w sums in one task), EDEVICE. */
+bz_status bz_count_codewords(bz_code *code, const bz_opts *o, bz_weight_count *res);
+
 /* ---- Autotuning of the enumeration's free parameters.
  *
  * Two parameters change only speed, never a result: the lane sums a lane keeps

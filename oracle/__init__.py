@@ -78,6 +78,11 @@ def _load():
         lib.or_splitmix64.restype = ctypes.c_uint64
         lib.or_trial_order.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, P(ctypes.c_int32)]
         lib.or_trial_order.restype = None
+        lib.or_count_weight.argtypes = [P(ctypes.c_uint64), ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                        P(ctypes.c_uint64), P(ctypes.c_uint64), ctypes.c_uint64,
+                                        P(ctypes.c_uint32)]
+        lib.or_count_weight.restype = ctypes.c_int
         lib.or_binomial.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         lib.or_binomial.restype = ctypes.c_uint64
         for f in (lib.or_certified_bound, lib.or_level_bound):
@@ -165,6 +170,25 @@ def prepare(G: np.ndarray, n: int, perm_trials: int = 0, perm_seed: int = 0):
         raise ValueError(f"oracle prepare failed with status {st}")
     nsets = mf.value + (1 if km.value > 0 else 0)
     return soc, mf.value, km.value, gam[: nsets * k].copy()
+
+
+def count_weight(G: np.ndarray, n: int, w: int, *, max_hits: int = 1 << 22, cap: int = 0,
+                 perm_trials: int = 0, perm_seed: int = 0):
+    """Step 8: (number of codewords of weight w, up to cap of them sorted, last level)."""
+    lib = _load()
+    G = _as_words(G)
+    k, ld = G.shape
+    cnt = ctypes.c_uint64()
+    lvl = ctypes.c_uint32()
+    out = np.zeros((max(cap, 1), OR_NW), dtype=np.uint64)
+    with _Permutations(perm_trials, perm_seed):
+        st = lib.or_count_weight(G.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k, n, ld, w,
+                                 max_hits, ctypes.byref(cnt),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cap,
+                                 ctypes.byref(lvl))
+    if st != OR_OK:
+        raise ValueError(f"oracle count failed with status {st}")
+    return int(cnt.value), out[: min(cap, cnt.value)], int(lvl.value)
 
 
 def splitmix64(state: int, count: int) -> list:

@@ -45,6 +45,13 @@
  *      weight of any codeword; the first codeword met with weight < U, or = U
  *      while no witness is held yet, becomes the witness.
  *
+ *   8. Codewords of a given weight w (not in the paper, which returns d only):
+ *      the tasks (Gamma_j, g) run in the order of step 3 and every sum of
+ *      weight w is collected, until the bound certified by the completed tasks
+ *      exceeds w. From then on every codeword not enumerated has weight > w,
+ *      so the distinct collected codewords are all codewords of weight w (a
+ *      codeword is met once in every Gamma_j where it is light enough, so
+ *      duplicates are removed by sorting).
  *   7. Random column permutations (Sec. 2.2: the implementation tries random
  *      permutations of the columns to find good information sets): with
  *      or_set_permutation_search(T, seed), step 1 is run T times, trial t
@@ -547,6 +554,69 @@ int or_task(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ldw,
     }
     free_code(&oc);
     return OR_OK;
+}
+
+static int cmp_row(const void *a, const void *b)
+{
+    const uint64_t *x = (const uint64_t *)a, *y = (const uint64_t *)b;
+    for (int w = OR_NW - 1; w >= 0; --w)
+        if (x[w] != y[w]) return x[w] < y[w] ? -1 : 1;
+    return 0;
+}
+
+/* Step 8 of the header: the number of codewords of weight w; up to cap of them
+ * (sorted as integers, most significant word last) go to out. Returns OR_OK,
+ * or OR_ELIMIT when more than max_hits weighted sums would have to be held. */
+int or_count_weight(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ldw, uint32_t w,
+                    uint64_t max_hits, uint64_t *count, uint64_t *out, uint64_t cap,
+                    uint32_t *last_level)
+{
+    if (!count || w == 0) return OR_EINVAL;
+    *count = 0;
+    or_code oc;
+    int st = prepare(G, (int)k, (int)n, (int)ldw, &oc);
+    if (st != OR_OK) return st;
+    int K = (int)k;
+    row_t *hits = (row_t *)malloc(sizeof(row_t) * (size_t)(max_hits ? max_hits : 1));
+    row_t *stack = (row_t *)malloc(sizeof(row_t) * (size_t)(K + 1));
+    int *c = (int *)malloc(sizeof(int) * (size_t)(K + 1));
+    uint64_t nh = 0;
+    int done = 0;
+    st = OR_OK;
+    for (int g = 1; g <= K && !done && st == OR_OK; ++g) {
+        if (last_level) *last_level = (uint32_t)g;
+        for (int j = 0; j < oc.nsets && !done && st == OR_OK; ++j) {
+            row_t *Gam = oc.gamma + (size_t)j * K;
+            for (int i = 0; i < g; ++i) c[i] = i;
+            int from = 0;
+            for (;;) {
+                for (int i = from; i < g; ++i) {
+                    if (i == 0) memcpy(stack[0], Gam[c[0]], sizeof(row_t));
+                    else row_xor(stack[i], stack[i - 1], Gam[c[i]]);
+                }
+                if ((uint32_t)row_weight(stack[g - 1]) == w) {
+                    if (nh >= max_hits) { st = OR_ELIMIT; break; }
+                    memcpy(hits[nh++], stack[g - 1], sizeof(row_t));
+                }
+                from = lex_next(c, g, K);
+                if (from < 0) break;
+            }
+            /* every codeword not met yet weighs at least the certified bound */
+            if (certified_bound(j, g, oc.m_f, oc.k_m, K) > (int)w) done = 1;
+        }
+    }
+    if (st == OR_OK) {
+        qsort(hits, (size_t)nh, sizeof(row_t), cmp_row);
+        uint64_t distinct = 0;
+        for (uint64_t i = 0; i < nh; ++i) {
+            if (i > 0 && cmp_row(hits[i], hits[i - 1]) == 0) continue;
+            if (out && distinct < cap) memcpy(out + distinct * OR_NW, hits[i], sizeof(row_t));
+            distinct++;
+        }
+        *count = distinct;
+    }
+    free(hits); free(stack); free(c); free_code(&oc);
+    return st;
 }
 
 /* The g-tuples Process_prefix visits for one prefix, in order. */

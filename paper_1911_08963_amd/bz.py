@@ -80,6 +80,14 @@ class DebugRect(ctypes.Structure):
                 ("head_blocks", ctypes.c_uint64), ("_reserved2", ctypes.c_uint64)]
 
 
+class WeightCount(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_uint32), ("last_level", ctypes.c_uint32),
+                ("count", ctypes.c_uint64), ("hits", ctypes.c_uint64),
+                ("combinations", ctypes.c_uint64), ("codewords", P(ctypes.c_uint64)),
+                ("codewords_cap", ctypes.c_uint64), ("codewords_len", ctypes.c_uint64),
+                ("search_s", ctypes.c_double)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_size_t), ("stats_cap", ctypes.c_uint32),
@@ -106,6 +114,7 @@ def _signatures(lib):
         "bz_min_distance_batch": ([P(vp), u32, P(Opts), P(Result), P(ctypes.c_int)], ctypes.c_int),
         "bz_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "bz_last_error": ([], ctypes.c_char_p),
+        "bz_count_codewords": ([vp, P(Opts), P(WeightCount)], ctypes.c_int),
         "bz_autotune": ([u32, u32, P(TuneEntry)], ctypes.c_int),
         "bz_autotune_get": ([u32, P(TuneEntry)], ctypes.c_int),
         "bz_autotune_set": ([P(TuneEntry)], ctypes.c_int),
@@ -317,6 +326,25 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
             o_.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
         outs.append(o_)
     return outs, [per[i] for i in range(cnt)]
+
+
+# ---------------------------------------------------------------- codewords of a given weight
+
+def count_codewords(code: Code, weight: int = 0, *, cap: int = 0, max_level: int = 0, stream=None) -> dict:
+    """bz_count_codewords: the number of codewords of weight `weight` (0 = d), and up to cap of them."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    o = _opts(0, max_level, stream.cuda_stream, None, None, 0, 0)
+    nw = (code.n + 63) // 64
+    buf = np.zeros((max(cap, 1), nw), dtype=np.uint64)
+    r = WeightCount()
+    r.weight = weight
+    r.codewords = buf.ctypes.data_as(P(ctypes.c_uint64)) if cap else None
+    r.codewords_cap = cap
+    _check(lib().bz_count_codewords(code.handle, ctypes.byref(o), ctypes.byref(r)))
+    return {"weight": r.weight, "count": r.count, "hits": r.hits, "combinations": r.combinations,
+            "last_level": r.last_level, "codewords": buf[: r.codewords_len].copy(), "search_s": r.search_s}
 
 
 # ---------------------------------------------------------------- autotuning

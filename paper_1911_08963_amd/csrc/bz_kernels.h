@@ -184,6 +184,26 @@ hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
 
+// ---- codewords of a given weight (bz_count_codewords)
+
+struct CollectHit {                // one combination of the target weight
+    uint64_t tile, q, h;           // its tile, lane-subset rank and head rank in the tile's rectangle
+};
+
+struct CollectArgs {
+    const uint32_t *rows;          // (k + 1) x W packed rows of Gamma_j (the last row zero)
+    const uint64_t *binom;
+    const Rect *rects;
+    unsigned long long *ncomb;     // combinations enumerated
+    unsigned long long *nhits;     // hits met (may exceed cap)
+    CollectHit *hits;
+    uint64_t cap, total_tiles;
+    uint32_t nrects, k, k_low, g, heads_per_tile, target;
+};
+
+// Slots per lane follow slots_for_w(W).
+hipError_t launch_collect(const CollectArgs &a, uint32_t W, uint32_t grid, hipStream_t st);
+
 // Issue-rate probe: 16 int32 lane operations per lane per trip.
 hipError_t launch_valu_probe(uint32_t iters, uint32_t blocks, uint32_t *sink, hipStream_t st);
 int valu_probe_blocks_per_cu();

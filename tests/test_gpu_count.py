@@ -1,0 +1,89 @@
+"""GPU: codewords of a given weight (bz_count_codewords) against the oracle.
+
+The count and the sorted list of codewords must equal the oracle's exactly
+(integers); for RM(3,7) the count must equal the closed form; every codeword
+returned must lie in the code with the asked weight.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import codes
+import oracle
+from paper_1911_08963_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1911_08963_amd import bz as _bz
+    _bz.lib()
+    return _bz
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rand(rng, n, k, systematic):
+    if systematic:
+        return inputs.pack_rows(inputs.random_systematic(rng, n, k))
+    while True:
+        A = rng.integers(0, 2, size=(k, n), dtype=np.uint8)
+        if inputs.gf2_rank_dense(A) == k:
+            return inputs.pack_rows(A)
+
+
+def test_count_equals_oracle(bz):
+    rng = np.random.default_rng(515)
+    for t in range(24):
+        n = int(rng.integers(10, 90))
+        k = int(rng.integers(2, min(n, 18) + 1))
+        G = _rand(rng, n, k, systematic=bool(t % 2))
+        code = bz.Code(G, n)
+        d = oracle.min_distance(G, n).d
+        for w in (0, d + 1):
+            _say("count case", t, "n", n, "k", k, "w", w)
+            got = bz.count_codewords(code, w, cap=1 << 12)
+            ww = got["weight"]
+            assert ww == (d if w == 0 else w)
+            cnt, ref, _ = oracle.count_weight(G, n, ww, cap=1 << 12)
+            assert got["count"] == cnt
+            nw = (n + 63) // 64
+            assert (got["codewords"] == ref[:, :nw]).all()
+            for x in got["codewords"][:16]:
+                assert int(np.bitwise_count(x).sum()) == ww and bf.in_code(x, G, n)
+        code.close()
+
+
+@pytest.mark.parametrize("name,builder,w,want", [
+    ("golay24", lambda: codes.extend(codes.golay23()), 8, 759),
+    ("rm26", lambda: codes.reed_muller(2, 6), 16, 2604),
+    ("rm37", lambda: codes.reed_muller(3, 7), 16, 94488),
+    ("whole_space10", lambda: codes.whole_space(10), 3, 120),
+])
+def test_count_textbook(bz, name, builder, w, want):
+    G, n, k, d = builder()
+    code = bz.Code(G, n)
+    got = bz.count_codewords(code, w, cap=8)
+    assert got["count"] == want
+    for x in got["codewords"]:
+        assert int(np.bitwise_count(x).sum()) == w and bf.in_code(x, G, n)
+    code.close()
+
+
+def test_count_plain128_minimum_weight(bz):
+    c = inputs.plain_code("plain128")
+    code = bz.Code(c.G, c.n)
+    got = bz.count_codewords(code, 0, cap=1 << 10)
+    _say("plain128 A_d", got["count"], "hits", got["hits"], "levels", got["last_level"])
+    assert got["weight"] == 16 and got["count"] >= 1
+    assert len(got["codewords"]) == got["count"]
+    for x in got["codewords"]:
+        assert int(np.bitwise_count(x).sum()) == 16 and bf.in_code(x, c.G, c.n)
+    code.close()

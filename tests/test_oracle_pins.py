@@ -339,3 +339,50 @@ def test_plain192_full_run_golden_is_consistent():
     pj, pg = full["stats"][-2][:2]
     assert (pj + 1) * (pg + 1) + (m_f - pj - 1) * pg < full["d"]
     assert min(s[2] for s in full["stats"]) == full["d"]
+
+
+# ---------------------------------------------------------------- codewords of a given weight
+
+def _rm_min_weight_count(r, m):
+    """A_{2^(m-r)} of RM(r, m) (MacWilliams & Sloane, Ch. 13, Thm. 9)."""
+    num = den = 1
+    for i in range(m - r):
+        num *= (1 << (m - i)) - 1
+        den *= (1 << (m - r - i)) - 1
+    return (1 << r) * num // den
+
+
+@pytest.mark.parametrize("name,builder,w,want", [
+    ("hamming7", codes.hamming7, 3, 7), ("hamming7", codes.hamming7, 4, 7),
+    ("golay23", codes.golay23, 7, 253), ("golay23", codes.golay23, 8, 506),
+    ("golay24", lambda: codes.extend(codes.golay23()), 8, 759),
+    ("golay24", lambda: codes.extend(codes.golay23()), 12, 2576),
+    ("rm26", lambda: codes.reed_muller(2, 6), 16, _rm_min_weight_count(2, 6)),
+    ("rm17", lambda: codes.reed_muller(1, 7), 64, 254),
+    ("simplex5", lambda: codes.simplex(5), 16, 31),
+])
+def test_count_weight_textbook(name, builder, w, want):
+    G, n, k, d = builder()
+    cnt, cws, lvl = oracle.count_weight(G, n, w, cap=4)
+    assert cnt == want
+    for x in cws:
+        assert int(np.bitwise_count(x).sum()) == w and bf.in_code(x, G, n)
+
+
+def test_count_weight_vs_bruteforce():
+    rng = np.random.default_rng(77)
+    for t in range(14):
+        n = int(rng.integers(8, 40))
+        k = int(rng.integers(2, min(n, 14) + 1))
+        G = _rand_code(rng, n, k)
+        cw = bf.all_codewords(G, k)[1:]
+        wts = bf.weights(cw)
+        d = int(wts.min())
+        for w in (d, d + 1, d + 2):
+            want = sorted(tuple(int(v) for v in x) for x, wt in zip(cw, wts) if wt == w)
+            cnt, got, _ = oracle.count_weight(G, n, w, cap=len(want) + 1)
+            assert cnt == len(want), (t, w)
+            keys = sorted(tuple(int(v) for v in x[: cw.shape[1]]) for x in got)
+            assert keys == want
+        # and with permuted information sets
+        assert oracle.count_weight(G, n, d, perm_trials=9, perm_seed=t)[0] == int((wts == d).sum())
