@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-cap", type=float, default=1e11,
                     help="serving admission: reject requests whose estimated cost exceeds this")
+    ap.add_argument("--no-count", dest="count_min_weight", action="store_false",
+                    help="skip counting the workload's minimum-weight codewords")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the fixed rules for slots per lane, tile size and tiles per task")
     ap.add_argument("--tiling", default="", metavar="SLOTS,TILES_PER_WAVE",
@@ -306,6 +308,18 @@ def main():
     if args.small_runs:
         for name in ("plain40", "plain128"):
             line["time_to_d_s"][name] = time_to_d_small(bz, inputs, name, args.small_runs)
+    if args.count_min_weight:
+        # the number of codewords of weight d: the search continued until the
+        # certified bound passes d, weight-d sums collected and de-duplicated
+        code = bz.Code(c.G, c.n)
+        cnt = bz.count_codewords(code, d, cap=1 << 16)
+        code.close()
+        for x in cnt["codewords"]:
+            assert int(np.bitwise_count(x).sum()) == d
+        line["min_weight_codewords"] = {"workload": args.workload, "weight": d, "count": cnt["count"],
+                                        "hits": cnt["hits"], "combinations": cnt["combinations"],
+                                        "last_level": cnt["last_level"], "seconds": cnt["search_s"]}
+        print(f"codewords of weight {d}: {cnt['count']} ({cnt['search_s']:.3f} s)", file=sys.stderr, flush=True)
     if args.batch:
         line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune)
     if args.serve_seconds > 0:
