@@ -19,9 +19,10 @@
 // finished its last task, which goes straight on with the next task. A wave
 // without a code first takes an unstarted one (a counter over the batch);
 // when none is left it helps: tasks with at least kShareTiles tiles are also
-// appended to a shared task log, which helpers walk from its head, moving the
-// head past exhausted entries. So every helper converges on the oldest large
-// task, and small tasks never leave their owner. Idle waves back off
+// appended to a shared task log, which helpers walk, moving the head past
+// exhausted entries. In a batch every helper starts at the head, so helpers
+// converge on the oldest large task, and small tasks never leave their owner;
+// the server spreads helpers over the live entries instead. Idle waves back off
 // exponentially. Waves leave when every code is finished or the cancel word is
 // set.
 //
@@ -36,7 +37,11 @@
 
 namespace bz {
 
-constexpr uint64_t kShareTiles = 8;   // tasks with this many tiles are offered to helpers
+// Tasks with this many tiles are offered to helpers: the batch shares only
+// large tasks (small ones stay with their owner, throughput first); the server
+// shares almost every task (a request's latency is its tasks' latency).
+template <bool SERVE>
+constexpr uint64_t kShareTiles = SERVE ? 2 : 8;
 
 // Wave-level atomics: one memory operation per wave, by construction. The
 // asm block (skipped when no lane is active) narrows exec to the wave's
@@ -279,7 +284,8 @@ __device__ void batch_advance(const BatchArgs &b, const ServeArgs *sv, uint32_t 
                             have_best != 0);
         if (lane == 0) __hip_atomic_fetch_add(b.done_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!done && uni64(b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1].total_tiles) >= kShareTiles)
+    if (!done &&
+        uni64(b.plans[(nj < m_f ? D.plan_full : D.plan_partial) + ng - 1].total_tiles) >= kShareTiles<SERVE>)
         log_append(b, code, epoch + 1, lane);
 }
 
@@ -470,7 +476,7 @@ __device__ bool serve_start(const ServeArgs &sv, uint64_t ticket, uint32_t lane)
         __hip_atomic_store(&t->tiles, (unsigned long long)P.total_tiles, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&S->cursor, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (uni64(P.total_tiles) >= kShareTiles) log_append(b, slot, 0, lane);
+    if (uni64(P.total_tiles) >= kShareTiles<true>) log_append(b, slot, 0, lane);
     return true;
 }
 
@@ -486,6 +492,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
     uint32_t cur = kNone;                              // the code this wave owns or helps
     uint32_t idle = 0;                                 // consecutive rounds without work
     uint64_t ticket = kNoTicket;                       // serving: the request this wave will start
+    uint64_t spread = uni64(((uint64_t)blockIdx.x << 8) ^ (threadIdx.x >> 6) ^ 0x9e3779b97f4a7c15ull);
     for (;;) {
         uint64_t pub = 0;
         if (SERVE) {
@@ -540,10 +547,19 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             }
         }
         if (!got) {
-            // help with the oldest large task in the log
-            uint64_t q = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            // help with a task in the log. Batch: the oldest (throughput).
+            // Server: start at a pseudo-random live entry and walk forward, so
+            // helpers spread over the active tasks (close to processor sharing:
+            // a young request's tasks are not queued behind old large ones).
+            const uint64_t head = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             const uint64_t end =
                 uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            uint64_t q = head;
+            if (SERVE && end > head + 1) {
+                spread = spread * 6364136223846793005ull + 1442695040888963407ull;   // per-wave LCG
+                const uint64_t live = umin64(end - head, 0xffffffffull);
+                q = head + (((spread >> 32) * live) >> 32);      // in [head, end) without a division
+            }
             for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
                 const unsigned long long ent = uni64(
                     __hip_atomic_load(b.log + (q & (b.log_cap - 1)), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));

@@ -46,6 +46,10 @@ constexpr uint64_t kLogCap = 1ull << 20;        // shared task log ring
 constexpr size_t kSlotBytes = 32 * 1024;        // staged payload of one request (n <= 256 needs < 25 KiB)
 constexpr uint32_t kEntryAlign = 8;             // plans start on 256-byte boundaries ...
 constexpr uint32_t kRectAlign = 16;             // ... in both tables (16 x 80 B = 5 x 256 B)
+// Head steps per tile of a served request: a tile is at most 64 x 16 x 256
+// sums (about 0.2 ms of one wave), so a newly published request waits little
+// for its ticket holder and a task splits finely between helpers.
+constexpr uint32_t kServeHeads = 256;
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -241,7 +245,7 @@ bz_status plan_for(bz_server *s, uint32_t k, uint32_t slots, PlanInfo &out, bool
     const uint32_t ro = (s->rects_used + kRectAlign - 1) / kRectAlign * kRectAlign;
     std::vector<bz::PlanEntry> pe;
     std::vector<bz::Rect> rc;
-    const uint32_t gmax = bz::build_level_plans(k, slots, 0, s->target_tiles, kServeMaxComb, ro, pe, rc);
+    const uint32_t gmax = bz::build_level_plans(k, slots, kServeHeads, s->target_tiles, kServeMaxComb, ro, pe, rc);
     if ((uint64_t)eo + pe.size() > kPlanEntries || (uint64_t)ro + rc.size() > kPlanRects)
         return fail(BZ_ENOMEM, "server plan tables full");
     std::memcpy(s->host_plans + eo, pe.data(), pe.size() * sizeof(bz::PlanEntry));
