@@ -119,8 +119,34 @@ typedef struct {
     uint32_t slots_per_lane;    /* combinations kept per lane (2, 4, 8, 16); 0 = autotuned or by row width */
     uint32_t heads_per_tile;    /* head steps per wave tile; 0 = autotuned or the planner's choice      */
     uint32_t tiles_per_task;    /* batch: tiles a task is cut into (about); 0 = autotuned or 64         */
+    uint32_t schedule;          /* bz_min_distance: BZ_SCHED_* (0 = equal-cost tiles, the default)       */
+    uint32_t prefix;            /* prefix size p of BZ_SCHED_1..8: absolute (D_*) or relative (S_*)     */
     uint32_t _reserved;
 } bz_opts;
+
+/* How bz_min_distance cuts a (Gamma_j, g) task and deals it to the device's
+ * waves. The default cuts the level's combinations into tiles of equal cost
+ * and deals them round-robin. The other eight are the distributed algorithms
+ * of Sec. 3 of arXiv:1911.08963 with one wave per worker: a task is a prefix,
+ * a p-subset c_1 < ... < c_p of the rows, that stands for every g-subset
+ * starting with it (C(k - 1 - c_p, g - p) of them; C(k - (g - p), p)
+ * prefixes); a wave adds the prefix rows once and enumerates the completions.
+ * Prefixes come in lexicographic order (Lex) or left-lexicographic order
+ * (Lle: the left-most element changes fastest). Dynamic schedules (D_*) hand
+ * them out from a shared counter, one per claim, or with 2CM two per claim,
+ * one from each end of the order. Static ones (S_*) deal them cyclically, or
+ * snake cyclically (SNC: every second round in reverse). D_* take p as the
+ * prefix size; S_* take it relative to g (the prefix has g - p elements).
+ * A prefix of g or more elements, or of none, makes the level one task. The
+ * result (d, bounds, statistics) is the same under every schedule; only the
+ * time changes. Schedules 1..8 need prefix >= 1, allocate their tilings on the
+ * device per search, and apply to bz_min_distance only (the batch call returns
+ * BZ_EINVAL; the server ignores the field). */
+enum {
+    BZ_SCHED_TILES = 0,
+    BZ_SCHED_D_LEX = 1, BZ_SCHED_D_LEX_2CM = 2, BZ_SCHED_D_LLE = 3, BZ_SCHED_D_LLE_2CM = 4,
+    BZ_SCHED_S_LEX = 5, BZ_SCHED_S_LEX_SNC = 6, BZ_SCHED_S_LLE = 7, BZ_SCHED_S_LLE_SNC = 8
+};
 
 typedef struct {
     uint16_t matrix, level;     /* j (0-based; the partial Gamma_m is j = m_f) and g        */

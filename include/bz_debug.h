@@ -1,9 +1,10 @@
 /*
  * bz_debug.h -- inspection and measurement entry points of libbz.
  *
- * The first two run without a GPU: they expose the host halves of bz_prepare
- * and of the level planner so that tests (and curious users) can check them
- * on a CPU. The last measures the device's sustained integer issue rate.
+ * The first three run without a GPU: they expose the host halves of
+ * bz_prepare, of the level planner and of the prefix schedules so that tests
+ * (and curious users) can check them on a CPU. The last measures the device's
+ * sustained integer issue rate.
  * Same conventions as bz.h (status codes, LSB-first uint64 rows, no retained
  * pointers, bz_last_error for details).
  */
@@ -44,6 +45,20 @@ typedef struct {
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                               uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used);
+
+/* The prefixes a schedule BZ_SCHED_1..8 hands out at level g of a Gamma
+ * matrix with k rows and prefix size p (relative for the static schedules),
+ * computed on the host with the device kernel's own mapping. Static: out[(w *
+ * turns + s) * e + i] is element i of the prefix worker w of `workers` takes
+ * at turn s. Dynamic: out[(c * 2 + s) * e + i] is element i of the s-th prefix
+ * (s < 2) of claim c, for claims c < workers. e = *pre_elems, the prefix's
+ * element count (0: the level is one task; then one entry per prefix, 0 for
+ * the task). -1 marks no prefix. *ntasks gets the number of prefixes.
+ * out may be NULL (counts only); cap is its length in entries. Errors: EINVAL
+ * (schedule not 1..8, k not 1..256, g not 1..min(k, 64), p or workers 0),
+ * ELIMIT (cap too small, too many prefixes). */
+bz_status bz_debug_schedule(uint32_t schedule, uint32_t k, uint32_t g, uint32_t p, uint32_t workers,
+                            uint32_t turns, int32_t *out, uint64_t cap, uint32_t *pre_elems, uint64_t *ntasks);
 
 /* Sustained int32 VALU rate of the current device on the enumeration's own
  * instruction pair (an XOR with a wave-uniform operand, then a popcount that

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_PKG, "libbz.so")
 BZ_OK, BZ_EINVAL, BZ_ERANK, BZ_ENOMEM, BZ_EDEVICE, BZ_ELIMIT, BZ_ECANCELED, BZ_EBUSY = \
     0, -1, -2, -3, -4, -5, -6, -7
 BZ_F_STATS, BZ_F_LEVEL_STOP, BZ_F_NO_WITNESS = 1, 2, 4
+# bz_opts.schedule: the equal-cost tiles (0) or the paper's eight distributed schedules
+SCHEDULES = {"tiles": 0, "D-Lex": 1, "D-Lex-2cm": 2, "D-Lle": 3, "D-Lle-2cm": 4,
+             "S-Lex": 5, "S-Lex-Snc": 6, "S-Lle": 7, "S-Lle-Snc": 8}
 BZ_MAX_N = 256
 
 P = ctypes.POINTER
@@ -44,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("cancel", P(ctypes.c_uint32)),
                 ("slots_per_lane", ctypes.c_uint32), ("heads_per_tile", ctypes.c_uint32),
-                ("tiles_per_task", ctypes.c_uint32), ("_reserved", ctypes.c_uint32)]
+                ("tiles_per_task", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
+                ("prefix", ctypes.c_uint32), ("_reserved", ctypes.c_uint32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -130,6 +134,8 @@ def _signatures(lib):
                                    P(u64), u32, P(u32), ctypes.c_size_t], ctypes.c_int),
         "bz_debug_plan_level": ([u32, u32, u32, u32, u64, P(DebugRect), u32, P(u32), P(u64),
                                  P(u32)], ctypes.c_int),
+        "bz_debug_schedule": ([u32, u32, u32, u32, u32, u32, P(ctypes.c_int32), u64, P(u32), P(u64)],
+                              ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -263,8 +269,11 @@ def _opts(flags, max_level, stream, ws, cancel, slots, heads, tiles=0) -> Opts:
 def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
                  witness: bool = True, max_level: int = 0, slots_per_lane: int = 0,
                  heads_per_tile: int = 0, stats_cap: int = 4096, stream=None,
-                 cancel=None, raise_on_error: bool = True) -> SearchResult:
-    """bz_min_distance on the current torch stream, with a torch-allocated workspace."""
+                 cancel=None, raise_on_error: bool = True, schedule=0, prefix: int = 0) -> SearchResult:
+    """bz_min_distance on the current torch stream, with a torch-allocated workspace.
+
+    schedule: 0 / "tiles", or one of the paper's schedules by number (1..8) or
+    name ("D-Lex", ..., "S-Lle-Snc", see SCHEDULES) with its prefix size."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -272,6 +281,8 @@ def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
     flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
         (0 if witness else BZ_F_NO_WITNESS)
     o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
+    o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    o.prefix = prefix
     wit = np.zeros(4, dtype=np.uint64)
     st_buf = (LevelStat * stats_cap)()
     r = Result()
@@ -534,3 +545,30 @@ def plan_level(k: int, g: int, slots: int = 8, heads_per_tile: int = 0, target_t
         r = rects[i]
         out.append({f: getattr(r, f) for f, _ in DebugRect._fields_ if not f.startswith("_")})
     return out, tt.value, hu.value
+
+
+def debug_schedule(schedule, k: int, g: int, p: int, workers: int, turns: int = 4):
+    """bz_debug_schedule: (pre_elems, ntasks, table). Static schedules: table[w][s] is
+    the prefix (tuple) worker w takes at turn s, or None. Dynamic: table[c] lists the
+    prefixes of claim c (one, two, or none). With pre_elems == 0 a prefix is ()."""
+    sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    pe, nt = ctypes.c_uint32(), ctypes.c_uint64()
+    _check(lib().bz_debug_schedule(sched, k, g, p, workers, turns, None, 0, ctypes.byref(pe), ctypes.byref(nt)))
+    e = max(pe.value, 1)
+    per = 2 if 1 <= sched <= 4 else turns
+    out = np.full(workers * per * e, -1, dtype=np.int32)
+    _check(lib().bz_debug_schedule(sched, k, g, p, workers, turns, out.ctypes.data_as(P(ctypes.c_int32)),
+                                   out.size, ctypes.byref(pe), ctypes.byref(nt)))
+    table = []
+    for w in range(workers):
+        row = []
+        for s_ in range(per):
+            ent = out[(w * per + s_) * e:(w * per + s_ + 1) * e]
+            if ent[0] < 0:
+                row.append(None)
+            else:
+                row.append(tuple(int(x) for x in ent) if pe.value else ())
+        if 1 <= sched <= 4:
+            row = [x for x in row if x is not None]
+        table.append(row)
+    return pe.value, nt.value, table

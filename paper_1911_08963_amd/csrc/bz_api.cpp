@@ -15,6 +15,7 @@
 #include "bz_host.h"
 #include "bz_internal.h"
 #include "bz_kernels.h"
+#include "bz_sched.h"
 
 namespace bz {
 
@@ -64,6 +65,7 @@ constexpr size_t kWsTask = 0;          // key, stats, ncomb, tile counter (u64 e
 constexpr size_t kWsRecover = 64;      // flag, len (u32), codeword (4 x u64)
 constexpr size_t kWsIndices = 128;     // up to 256 u32 row indices
 constexpr size_t kWsRecoverRect = 1280;
+constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
 constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
 constexpr size_t kWsBytes = kWsRects + kMaxRects * sizeof(bz::Rect);
@@ -85,6 +87,7 @@ struct Best {
     uint32_t j = 0, g = 0, slots = 0, ht = 0;
     uint64_t tile = 0;
     bz::Rect rect{};
+    std::vector<uint32_t> pre;       // rows of the winning prefix task (schedules 1..8)
 };
 
 
@@ -193,6 +196,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
     if (opt.slots_per_lane)
         return fail(BZ_EINVAL, "the batched search chooses slots per lane itself (pass 0)");
+    if (opt.schedule != BZ_SCHED_TILES) return fail(BZ_EINVAL, "schedules 1..8 apply to bz_min_distance only");
     const bool stats = opt.flags & BZ_F_STATS;
     const double t0 = now_s();
     for (uint32_t i = 0; i < count; ++i) {
@@ -483,6 +487,14 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     if (opt.slots_per_lane && opt.slots_per_lane != 2 && opt.slots_per_lane != 4 && opt.slots_per_lane != 8 &&
         opt.slots_per_lane != 16)
         return fail(BZ_EINVAL, "slots_per_lane must be 0, 2, 4, 8 or 16");
+    const bool use_sched = opt.schedule != BZ_SCHED_TILES;
+    uint32_t sched_dist = 0, sched_order = 0;
+    bool sched_dynamic = false;
+    if (use_sched) {
+        if (!bz::sched_parts(opt.schedule, sched_dist, sched_order, sched_dynamic))
+            return fail(BZ_EINVAL, "schedule must be 0..8");
+        if (opt.prefix == 0) return fail(BZ_EINVAL, "schedules 1..8 need a prefix size >= 1");
+    }
     const bool stats = opt.flags & BZ_F_STATS, level_stop = opt.flags & BZ_F_LEVEL_STOP;
     const bool want_witness = !(opt.flags & BZ_F_NO_WITNESS) && res->witness;
     const uint32_t n = c->n, k = c->k, m_f = c->num_full, k_m = c->partial_rank;
@@ -543,6 +555,12 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     }
 
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots, tiles/wave) -> plan
+    std::map<std::pair<uint32_t, uint32_t>, bz::SchedPlan> splans;            // (g, slots) -> prefix tasks
+    struct DevBuf {
+        char *p = nullptr;
+        size_t cap = 0;
+        ~DevBuf() { if (p) (void)hipFree(p); }
+    } sbuf;                                                                    // schedule tilings
     const uint64_t resident_waves = (uint64_t)dc.cus * 32;
     bool done = false;
     for (uint32_t g = 1; g <= k && L < U && !done; ++g) {
@@ -555,36 +573,78 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
             uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
             if (!opt.slots_per_lane && !opt.heads_per_tile) (void)bz::tuned_choice(W, slots, per_wave);
             if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
-            auto key = std::make_tuple(g, slots, per_wave);
-            if (!plans.count(key)) {
-                std::string err;
-                bz::LevelPlan p;
-                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
-                    return fail(BZ_ELIMIT, err);
-                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
-                plans[key] = std::move(p);
-            }
-            const bz::LevelPlan &plan = plans[key];
-            BZ_HIP(hipMemcpyAsync(d_rects, plan.rects.data(), plan.rects.size() * sizeof(bz::Rect),
-                                  hipMemcpyHostToDevice, st));
+            if (use_sched) slots = bz::slots_for_w(W);      // the schedule kernel's fixed lane sums
+            const bz::LevelPlan *plan = nullptr;
+            const bz::SchedPlan *sp = nullptr;
             BZ_HIP(bz::launch_task_init(d_key, d_stats, d_ncomb, d_ctr, st));
             bz::TaskArgs a{};
             a.rows = (const uint32_t *)c->dev + c->packed_off[j];
             a.binom = dc.binom;
-            a.rects = d_rects;
             a.key = d_key; a.stats = d_stats; a.ncomb = d_ncomb; a.tile_ctr = d_ctr;
             a.cancel = (const uint32_t *)opt.cancel;
-            a.nrects = (uint32_t)plan.rects.size();
             a.k = k; a.k_low = c->k_low(j); a.g = g;
-            a.heads_per_tile = plan.heads_per_tile;
-            a.total_tiles = plan.total_tiles;
             a.u_prev = U;
             a.exit_at = stats ? 0u : Lcert;
-            const uint64_t blocks = (plan.total_tiles + 3) / 4;
-            const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
-            BZ_HIP(hipEventRecord(ev0, st));
-            BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
-            BZ_HIP(hipEventRecord(ev1, st));
+            if (use_sched) {
+                auto skey = std::make_pair(g, slots);
+                if (!splans.count(skey)) {
+                    std::string err;
+                    bz::SchedPlan p;
+                    if (!bz::build_sched_plan(k, g, sched_dynamic, opt.prefix, slots, p, err))
+                        return fail(BZ_ELIMIT, err);
+                    splans[skey] = std::move(p);
+                }
+                sp = &splans[skey];
+                const size_t eb = align256(sp->entries.size() * sizeof(bz::PlanEntry));
+                const size_t need = eb + sp->rects.size() * sizeof(bz::Rect);
+                if (need > sbuf.cap) {
+                    if (sbuf.p) (void)hipFree(sbuf.p);
+                    sbuf.p = nullptr;
+                    sbuf.cap = 0;
+                    if (hipMalloc((void **)&sbuf.p, need) != hipSuccess) return fail(BZ_ENOMEM, "schedule tilings");
+                    sbuf.cap = need;
+                }
+                BZ_HIP(hipMemcpyAsync(sbuf.p, sp->entries.data(), sp->entries.size() * sizeof(bz::PlanEntry),
+                                      hipMemcpyHostToDevice, st));
+                BZ_HIP(hipMemcpyAsync(sbuf.p + eb, sp->rects.data(), sp->rects.size() * sizeof(bz::Rect),
+                                      hipMemcpyHostToDevice, st));
+                bz::SchedArgs sa{};
+                sa.t = a;
+                sa.plans = (const bz::PlanEntry *)sbuf.p;
+                sa.rects = (const bz::Rect *)(sbuf.p + eb);
+                sa.ntasks = sp->ntasks;
+                sa.stride = sp->stride;
+                sa.pre = sp->pre;
+                sa.dist = sched_dist;
+                sa.order = sched_order;
+                const size_t lds = bz::enum_lds_bytes(k, g, W);
+                const uint32_t grid = (uint32_t)dc.cus * (uint32_t)bz::sched_blocks_per_cu(W, j >= m_f, stats, lds);
+                BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_sched(sa, W, j >= m_f, stats, grid, st));
+                BZ_HIP(hipEventRecord(ev1, st));
+            } else {
+                auto key = std::make_tuple(g, slots, per_wave);
+                if (!plans.count(key)) {
+                    std::string err;
+                    bz::LevelPlan p;
+                    if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
+                        return fail(BZ_ELIMIT, err);
+                    if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
+                    plans[key] = std::move(p);
+                }
+                plan = &plans[key];
+                BZ_HIP(hipMemcpyAsync(d_rects, plan->rects.data(), plan->rects.size() * sizeof(bz::Rect),
+                                      hipMemcpyHostToDevice, st));
+                a.rects = d_rects;
+                a.nrects = (uint32_t)plan->rects.size();
+                a.heads_per_tile = plan->heads_per_tile;
+                a.total_tiles = plan->total_tiles;
+                const uint64_t blocks = (plan->total_tiles + 3) / 4;
+                const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
+                BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
+                BZ_HIP(hipEventRecord(ev1, st));
+            }
             unsigned long long words[3];
             BZ_HIP(hipMemcpyAsync(words, d_key, sizeof(words), hipMemcpyDeviceToHost, st));
             BZ_HIP(hipStreamSynchronize(st));
@@ -594,7 +654,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
             res->launches++;
             const uint32_t tmin = words[0] == ~0ull ? 0xffffffffu : (uint32_t)(words[0] >> bz::kTileBits);
             const uint64_t ncomb = words[2];
-            const bool complete = ncomb == plan.combinations;
+            const bool complete = ncomb == bz::binom_sat(k, g);
             res->combinations += ncomb;
             if (res->stats && res->stats_len < res->stats_cap) {
                 bz_level_stat &s = res->stats[res->stats_len];
@@ -606,13 +666,31 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
             if (tmin < U || (tmin == U && !best.have)) {
                 U = tmin;
                 best.have = true; best.j = j; best.g = g; best.tile = words[0] & bz::kTileMask;
-                best.slots = slots; best.ht = plan.heads_per_tile;
-                size_t lo = 0, hi = plan.rects.size() - 1;
+                best.slots = slots;
+                const bz::Rect *rr = nullptr;
+                size_t nr = 0;
+                if (sp) {
+                    // key tile = prefix task * stride + tile of that task's completion plan
+                    const uint64_t task = best.tile / sp->stride;
+                    best.tile -= task * sp->stride;
+                    uint32_t lo = 0;
+                    bz::sched_prefix(*sp, k, g, sched_order, task, best.pre, lo);
+                    const bz::PlanEntry &e = sp->entries[lo];
+                    rr = sp->rects.data() + e.rect_off;
+                    nr = e.nrects;
+                    best.ht = e.heads_per_tile;
+                } else {
+                    best.pre.clear();
+                    rr = plan->rects.data();
+                    nr = plan->rects.size();
+                    best.ht = plan->heads_per_tile;
+                }
+                size_t lo = 0, hi = nr - 1;
                 while (lo < hi) {
                     size_t mid = (lo + hi + 1) / 2;
-                    if (plan.rects[mid].tile_begin <= best.tile) lo = mid; else hi = mid - 1;
+                    if (rr[mid].tile_begin <= best.tile) lo = mid; else hi = mid - 1;
                 }
-                best.rect = plan.rects[lo];
+                best.rect = rr[lo];
             }
             if (opt.cancel && *opt.cancel && !complete) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
             if (!complete) {
@@ -651,6 +729,11 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ra.indices = (uint32_t *)(ws + kWsIndices);
         ra.tile = best.tile; ra.slots = best.slots; ra.heads_per_tile = best.ht;
         ra.W = c->W(j); ra.k_low = c->k_low(j); ra.target = U;
+        ra.pre_n = (uint32_t)best.pre.size();
+        ra.pre_rows = (const uint32_t *)(ws + kWsPreRows);
+        if (ra.pre_n)
+            BZ_HIP(hipMemcpyAsync(ws + kWsPreRows, best.pre.data(), ra.pre_n * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                  st));
         BZ_HIP(hipMemcpyAsync(ws + kWsRecoverRect, &best.rect, sizeof(bz::Rect), hipMemcpyHostToDevice, st));
         BZ_HIP(hipMemsetAsync(ws + kWsRecover, 0, 64, st));
         BZ_HIP(bz::launch_recover(ra, st));

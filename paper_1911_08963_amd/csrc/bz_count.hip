@@ -36,8 +36,10 @@ __global__ __launch_bounds__(kBlock) void bz_collect_kernel(CollectArgs a) {
     for (uint64_t it = first; it < a.total_tiles; it += stride) {
         const uint64_t tile = uni64(it);
         const TileGeom t = locate_tile(a.nrects, rect_p, tile);
-        uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS];
-        const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, P, low, pen);
+        uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS], none[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) none[w] = 0;
+        const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, none, 0u, P, low, pen);
         const uint64_t h0 = t.hb * a.heads_per_tile;
         const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
         const uint64_t base = t.lb * (kWaveSize * SLOTS);

@@ -31,6 +31,23 @@ uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, 
                            uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
                            std::vector<Rect> &rects);
 
+// A (Gamma_j, g) task cut into the prefix tasks of one of the paper's
+// schedules (bz_sched.h): entries[lo] tiles the completions of a prefix whose
+// last element is lo - 1 (entries[0]: the empty prefix), rect_off counted in
+// rects; the other entries are zero.
+struct SchedPlan {
+    uint32_t pre = 0;                 // prefix elements (0: the level is one task)
+    uint64_t ntasks = 0;              // C(k - (g - pre), pre)
+    uint64_t stride = 0;              // tiles of the largest completion plan
+    std::vector<PlanEntry> entries;   // k + 1
+    std::vector<Rect> rects;
+};
+bool build_sched_plan(uint32_t k, uint32_t g, bool dynamic, uint32_t prefix, uint32_t slots, SchedPlan &out,
+                      std::string &err);
+// The rows of prefix task `task` (ascending) and its completion plan's index.
+void sched_prefix(const SchedPlan &sp, uint32_t k, uint32_t g, uint32_t order, uint64_t task,
+                  std::vector<uint32_t> &rows, uint32_t &lo);
+
 // The autotuned (slots per lane, tiles per resident wave) for row width W, if any.
 bool tuned_choice(uint32_t W, uint32_t &slots, uint32_t &tiles_per_wave);
 // The autotuned tiles per task of batches (0 = none).

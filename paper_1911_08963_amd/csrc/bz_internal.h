@@ -60,6 +60,9 @@ struct LevelPlan {
 
 bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                 uint64_t target_tiles, LevelPlan &out, std::string &err);
+// The same for the g-subsets of rows [lo, lo + n) (plan_level is lo = 0, n = k).
+bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
+                uint64_t target_tiles, LevelPlan &out, std::string &err);
 
 // C(a, b) with saturation at kBinomSat for values >= 2^63.
 uint64_t binom_sat(uint32_t a, uint32_t b);

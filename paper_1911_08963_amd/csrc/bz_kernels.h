@@ -35,6 +35,8 @@ struct RecoverArgs {
     unsigned long long *codeword;   // kHostWords words
     uint64_t tile;
     uint32_t slots, heads_per_tile, W, k_low, target;
+    uint32_t pre_n;              // rows of a prefix task joined to every combination (0 = none)
+    const uint32_t *pre_rows;    // their indices (device)
 };
 
 // ---- batched persistent search (bz_min_distance_batch)
@@ -183,6 +185,27 @@ size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W);
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
+
+// ---- the paper's prefix-task schedules (bz_sched.hip, bz_sched.h)
+
+// One (Gamma_j, g) task run as prefix tasks dealt to waves. plans[lo] tiles
+// the (g - pre)-subsets of rows [lo, k) (unused entries zero); a prefix whose
+// last element is c uses plans[c + 1], the empty prefix plans[0]. The task
+// key's tile field is task * stride + tile within the prefix's plan.
+struct SchedArgs {
+    TaskArgs t;                  // rows, binom, key, stats, ncomb, tile_ctr (claims), cancel, k, k_low, g, u_prev, exit_at
+    const PlanEntry *plans;      // k + 1 entries
+    const Rect *rects;           // every plan's rectangles
+    uint64_t ntasks;             // C(k - (g - pre), pre)
+    uint64_t stride;             // tiles of the largest suffix plan
+    uint32_t pre;                // prefix elements (0: the level is one task)
+    uint32_t dist, order;        // kDist*, kOrder* (bz_sched.h)
+    uint32_t _pad;
+};
+
+hipError_t launch_sched(const SchedArgs &a, uint32_t W, bool partial, bool stats, uint32_t grid, hipStream_t st);
+// Work-groups of the schedule kernel one CU holds (its waves are the workers).
+int sched_blocks_per_cu(uint32_t W, bool partial, bool stats, size_t lds);
 
 // ---- codewords of a given weight (bz_count_codewords)
 

@@ -69,9 +69,10 @@ __global__ void bz_task_init_kernel(unsigned long long *key, unsigned long long 
 }
 
 // Witness recovery: one thread per combination of the winning tile, each
-// computed from scratch (no shared state with the enumeration kernel). The
-// first thread whose combination has the target weight writes its row
-// indices and the codeword (XOR of the full rows, original coordinates).
+// computed from scratch (no shared state with the enumeration kernel), joined
+// to the rows of the tile's prefix task when it has one. The first thread
+// whose combination has the target weight writes its row indices and the
+// codeword (XOR of the full rows, original coordinates).
 __global__ void bz_recover_kernel(RecoverArgs a) {
     const uint64_t lane_items = (uint64_t)kWaveSize * a.slots;
     const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,6 +104,12 @@ __global__ void bz_recover_kernel(RecoverArgs a) {
             hi = lo - 1;
         }
     };
+    for (uint32_t i = 0; i < a.pre_n; ++i) {          // a prefix task's rows
+        const uint32_t row = a.pre_rows[i];
+        idx[cnt++] = row;
+        for (uint32_t w = 0; w < a.W; ++w) word[w] ^= a.rows[row * a.W + w];
+        ident += row < a.k_low ? 1u : 0u;
+    }
     add_subset(q, R.lane_t, R.lane_off, R.lane_n);
     if (R.head_t) add_subset(h, R.head_t, R.head_off, R.head_n);
     uint32_t wgt = ident;

@@ -73,16 +73,21 @@ struct Builder {
 
 bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                 uint64_t target_tiles, LevelPlan &out, std::string &err) {
+    return plan_range(0, k, g, slots, heads_per_tile, target_tiles, out, err);
+}
+
+bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
+                uint64_t target_tiles, LevelPlan &out, std::string &err) {
     out = LevelPlan{};
-    out.k = k; out.g = g; out.slots = slots;
-    if (g == 0 || g > k) { err = "level out of range"; return false; }
-    uint64_t total = binom_sat(k, g);
+    out.k = lo + n; out.g = g; out.slots = slots;
+    if (g == 0 || g > n) { err = "level out of range"; return false; }
+    uint64_t total = binom_sat(n, g);
     if (total == kBinomSat) { err = "C(k, g) >= 2^63"; return false; }
     if (g > (uint32_t)kBinomT) { err = "level above the device binomial table"; return false; }
     Builder b;
     b.threshold = 4ull * kWaveSize * slots;
     b.out = &out.rects;
-    b.all(0, k, g);
+    b.all(lo, n, g);
     if (b.overflow) { err = "a factor count overflows 2^63"; return false; }
     uint64_t lane_items = (uint64_t)kWaveSize * slots;
     uint32_t ht = heads_per_tile;

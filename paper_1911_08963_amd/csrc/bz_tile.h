@@ -150,9 +150,12 @@ __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_
 // test. (With an "if (valid)" per lane here the optimizer specialised the
 // tile's uniform combination count per divergent path and the wave took the
 // wrong path's value.)
+// pre / pre_low: the XOR and the count below k_low of rows joined to every
+// combination of the tile (a prefix task's prefix; zero otherwise).
 template <int W, int SLOTS>
 __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low, const uint32_t *srow,
                                                const uint64_t *sbin, uint32_t bt, uint32_t lane,
+                                               const uint32_t (&pre)[W], uint32_t pre_low,
                                                uint32_t (&P)[SLOTS][W], uint32_t (&low)[SLOTS],
                                                uint32_t (&pen)[SLOTS]) {
     const uint64_t base = t.lb * (kWaveSize * SLOTS);
@@ -164,8 +167,8 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
         const uint64_t q = first + lane;
         const bool valid = q < t.lane_count;
 #pragma unroll
-        for (int w = 0; w < W; ++w) P[s][w] = 0;
-        low[s] = 0;
+        for (int w = 0; w < W; ++w) P[s][w] = pre[w];
+        low[s] = pre_low;
         pen[s] = valid ? 0u : 0x10000u;
         if (first >= t.lane_count) continue;      // uniform: a slot with no valid lane
         uint64_t r = valid ? q : 0ull;
@@ -278,13 +281,32 @@ __device__ __forceinline__ bool head_walk(const TileGeom &t, cptr32 rows, cptr64
     return false;
 }
 
-template <int W, int SLOTS, bool PARTIAL, bool STATS>
-__device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
-                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
-                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
+// A wave's running totals of tiles whose counter updates it defers: combinations,
+// and the minimum weight with the number of combinations reaching it (all uniform).
+struct TileSum {
+    uint64_t comb = 0;
+    uint32_t min = 0xffffffffu, cnt = 0;
+    __device__ void add(uint64_t c, uint32_t m, uint32_t n) {
+        comb += c;
+        if (m < min) { min = m; cnt = n; }
+        else if (m == min) cnt += n;
+    }
+};
+
+// One tile whose combinations all contain the rows of pre (XOR pre, pre_low of
+// them below k_low); the task key records key_tile for it. With DEFER the
+// combination count and statistics go to *sum instead of the task's counters
+// (a wave running many small tiles flushes them once: every tile's atomic on
+// the same word would serialise the waves).
+template <int W, int SLOTS, bool PARTIAL, bool STATS, bool DEFER = false>
+__device__ __forceinline__ void run_tile_pre(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
+                                             const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
+                                             cptr_rect rect_p, uint64_t tile, uint32_t lane,
+                                             const uint32_t (&pre)[W], uint32_t pre_low, uint64_t key_tile,
+                                             TileSum *sum = nullptr) {
     const TileGeom t = locate_tile(a.nrects, rect_p, tile);
     uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS];
-    const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, P, low, pen);
+    const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, pre, pre_low, P, low, pen);
     const uint64_t h0 = t.hb * a.heads_per_tile;
     const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
     const uint64_t tile_comb = (uint64_t)nvalid * count;
@@ -345,13 +367,27 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
     const uint32_t tmin = uni(wave_min(lane_best));
     uint32_t tcnt = 0;
     if (STATS) tcnt = uni(wave_sum(lane_best == tmin ? lane_cnt : 0u));
+    if (DEFER) sum->add(tile_comb, tmin, tcnt);
     if (lane == 0) {
         // most tiles do not lower the key: read it first, update only when needed
-        const unsigned long long mine = ((unsigned long long)tmin << kTileBits) | tile;
+        const unsigned long long mine = ((unsigned long long)tmin << kTileBits) | key_tile;
         if (mine < __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(a.key, mine);
-        atomicAdd(a.ncomb, (unsigned long long)tile_comb);
-        if (STATS) stats_merge(a.stats, tmin, tcnt);
+        if (!DEFER) {
+            atomicAdd(a.ncomb, (unsigned long long)tile_comb);
+            if (STATS) stats_merge(a.stats, tmin, tcnt);
+        }
     }
+}
+
+// A tile of the task's own tiling (no prefix).
+template <int W, int SLOTS, bool PARTIAL, bool STATS>
+__device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
+                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
+                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
+    uint32_t none[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) none[w] = 0;
+    run_tile_pre<W, SLOTS, PARTIAL, STATS>(a, rows, binom_c, srow, sbin, bt, rect_p, tile, lane, none, 0u, tile);
 }
 
 // Finds one combination of the tile whose weight is target (the tile is

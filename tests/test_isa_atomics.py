@@ -1,4 +1,4 @@
-"""The persistent kernels issue each atomic from one lane (compiled code check, CPU).
+"""The persistent and schedule kernels issue each atomic from one lane (compiled code check, CPU).
 
 Work claims, completions and log appends are wave-wide operations on a few hot
 words. Each must reach memory as one atomic per wave: an atomic executed by
@@ -24,15 +24,19 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC) and not shutil.which("hipcc"), reason="hipcc not installed")
-def test_persistent_kernel_atomics_are_single_lane(tmp_path):
-    out = tmp_path / "bz_batch.s"
+@pytest.mark.parametrize("source,pattern,count", [
+    ("bz_batch.hip", r"^(_ZN2bz\d+bz_(?:batch|serve)_kernel\w+):", 4),
+    ("bz_sched.hip", r"^(_ZN2bz\d+bz_sched_kernel\w+):", 32),
+])
+def test_persistent_kernel_atomics_are_single_lane(tmp_path, source, pattern, count):
+    out = tmp_path / (source + ".s")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "--cuda-device-only", "-S",
-           os.path.join(CSRC, "bz_batch.hip"), "-o", str(out)]
+           os.path.join(CSRC, source), "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
     s = out.read_text()
-    kernels = re.findall(r"^(_ZN2bz\d+bz_(?:batch|serve)_kernel\w+):", s, re.M)
-    assert len(kernels) == 4
+    kernels = re.findall(pattern, s, re.M)
+    assert len(kernels) == count
     for k in kernels:
         body = s[s.index(k + ":"):s.index(".Lfunc_end", s.index(k + ":"))].splitlines()
         n = 0
@@ -40,7 +44,7 @@ def test_persistent_kernel_atomics_are_single_lane(tmp_path):
             if "_atomic_" not in line or line.strip().startswith(";"):
                 continue
             n += 1
-            ctx = " ".join(body[max(0, i - 14):i])
+            ctx = " ".join(body[max(0, i - 24):i])
             assert ("v_mbcnt" in ctx or "s_and_saveexec" in ctx or "s_lshl_b64 exec" in ctx), \
                 f"{k}: atomic without a single-lane region: {line.strip()}"
         assert n > 0
