@@ -12,7 +12,8 @@ Printed: one JSON line with value = combinations enumerated per second of
 wall time over the timed steps, ms_per_step = time-to-d, the roofline of the
 enumeration kernel (int32 VALU: 2W+1 operations per combination, measured
 with HIP events on the search stream) and the CPU oracle timed on a bounded
-sample of the same code. Beside it: the batched workload in one persistent
+sample of the same code. Beside it: the paper's eight prefix schedules
+against the default tiles (time-to-d), the batched workload in one persistent
 launch against plain per-code launches (codes/s), and a Poisson serving
 stream through the resident server (p50/p99 latency, codes/s).
 """
@@ -105,6 +106,32 @@ def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True) 
     }
 
 
+# Prefix sizes for the paper's schedules on this GPU's 5-8k waves: the fastest of
+# a sweep on each workload (absolute for D-*, relative to g for S-*).
+SCHED_PREFIX = {"plain192": {"D": 4, "S": 6}, "plain128": {"D": 2, "S": 5}}
+
+
+def schedules_comparison(bz, c, workload: str, d: int) -> dict:
+    """The paper's eight distributed schedules (Sec. 3) with the device's waves as workers,
+    against the default equal-cost tiles: time-to-d of the same code, one run each."""
+    pre = SCHED_PREFIX[workload]
+    code = bz.Code(c.G, c.n)
+    out = {"workload": workload, "prefix": {"dynamic (absolute)": pre["D"], "static (relative)": pre["S"]},
+           "seconds": {}}
+    r = bz.min_distance(code)
+    out["seconds"]["tiles"] = r.search_s
+    for name in ("D-Lex", "D-Lex-2cm", "D-Lle", "D-Lle-2cm", "S-Lex", "S-Lex-Snc", "S-Lle", "S-Lle-Snc"):
+        r = bz.min_distance(code, schedule=name, prefix=pre[name[0]])
+        assert r.d == d
+        out["seconds"][name] = r.search_s
+        print(f"schedule {name}: {r.search_s:.3f} s", file=sys.stderr, flush=True)
+    code.close()
+    best = min((v, k) for k, v in out["seconds"].items() if k != "tiles")
+    out["best_schedule"] = best[1]
+    out["tiles_speedup_over_best"] = best[0] / out["seconds"]["tiles"]
+    return out
+
+
 def time_to_d_small(bz, inputs, name: str, runs: int) -> dict:
     """Median time-to-d of a small plain workload over many runs (prepare and search split)."""
     c = inputs.plain_code(name)
@@ -167,6 +194,8 @@ def main():
                     help="serving admission: reject requests whose estimated cost exceeds this")
     ap.add_argument("--no-count", dest="count_min_weight", action="store_false",
                     help="skip counting the workload's minimum-weight codewords")
+    ap.add_argument("--no-schedules", dest="schedules", action="store_false",
+                    help="skip the paper's eight prefix schedules (about 15 s)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the fixed rules for slots per lane, tile size and tiles per task")
     ap.add_argument("--tiling", default="", metavar="SLOTS,TILES_PER_WAVE",
@@ -320,6 +349,8 @@ def main():
                                         "hits": cnt["hits"], "combinations": cnt["combinations"],
                                         "last_level": cnt["last_level"], "seconds": cnt["search_s"]}
         print(f"codewords of weight {d}: {cnt['count']} ({cnt['search_s']:.3f} s)", file=sys.stderr, flush=True)
+    if args.schedules and args.workload in SCHED_PREFIX:
+        line["schedules"] = schedules_comparison(bz, c, args.workload, d)
     if args.batch:
         line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune)
     if args.serve_seconds > 0:

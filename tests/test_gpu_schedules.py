@@ -153,3 +153,17 @@ def test_schedule_errors(bz):
         arr = (ctypes.c_void_p * 1)(code.handle)
         bz._check(bz.lib().bz_min_distance_batch(arr, 1, ctypes.byref(o), res, per))
     code.close()
+
+
+def test_plain192_best_schedules(bz):
+    """The full [192, 64] search (d = 35) under the fastest dynamic and static schedule."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "plain192_oracle.json")))
+    c = inputs.plain_code("plain192")
+    code = bz.Code(c.G, c.n)
+    for sched, prefix in (("D-Lle-2cm", 4), ("S-Lle-Snc", 6)):
+        _say("case plain192", sched, prefix)
+        got = bz.min_distance(code, schedule=sched, prefix=prefix)
+        assert got.d == gold["d"] == 35
+        assert (got.lower_bound, got.upper_bound) == (gold["lower_bound"], gold["upper_bound"])
+        _check_witness(got, c.G, c.n)
+    code.close()
