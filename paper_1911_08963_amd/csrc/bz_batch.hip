@@ -22,7 +22,7 @@
 // appended to a shared task log, which helpers walk, moving the head past
 // exhausted entries. In a batch every helper starts at the head, so helpers
 // converge on the oldest large task, and small tasks never leave their owner;
-// the server spreads helpers over the live entries instead. Idle waves back off
+// the server spreads helpers over the newest entries instead. Idle waves back off
 // exponentially. Waves leave when every code is finished or the cancel word is
 // set.
 //
@@ -43,6 +43,13 @@ namespace bz {
 // shares almost every task (a request's latency is its tasks' latency).
 template <bool SERVE>
 constexpr uint64_t kShareTiles = SERVE ? 2 : 8;
+
+// Log entries a server helper samples from: the newest this many.
+constexpr uint64_t kServeWindow = 256;
+// Tickets held ahead of the published count: a holder takes no tiles (it only
+// waits for its request), so a published request starts within a poll, and
+// every other wave is free to help with tiles of any length.
+constexpr uint64_t kTicketsAhead = 64;
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
 // later matrices at level g - 1 (j == m_f is the partial matrix).
@@ -115,7 +122,7 @@ __device__ __forceinline__ void log_append(const BatchArgs &b, uint32_t code, ui
     const uint64_t head = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t tail = uni64(__hip_atomic_load(b.log_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (tail - head >= b.log_cap) return;          // full: the owner runs the task alone
-    const unsigned long long pos = wave_fetch_add64(b.log_tail, 1ull, lane);
+    const unsigned long long pos = wave_fetch_add64_relaxed(b.log_tail, 1ull);
     if (lane == 0)
         __hip_atomic_store(b.log + (pos & (b.log_cap - 1)), (unsigned long long)((((uint64_t)code) << 24) | epoch) + 1ull,
                            __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -228,7 +235,8 @@ __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uin
     const unsigned long long tw0 =
         uni64(__hip_atomic_load(&S->slot[e0 & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
-    const unsigned long long w = wave_fetch_add64(&S->cursor, 1ull, lane);
+    // relaxed: the acquire load of the slot's tile word below orders what follows
+    const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, 1ull);
     const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
     if (e == kDoneEpoch) return false;
     const unsigned long long tw =
@@ -316,12 +324,15 @@ __device__ __forceinline__ void wave_copy_in(uint64_t *dst, const uint64_t *src,
 constexpr uint64_t kPollTicks = 500;          // wall-clock ticks between polls of the host words (5 us at 100 MHz)
 
 // The wave's view of the host's published count and shutdown word. Device
-// copies are read every time; at most one wave per kPollTicks reads the host
-// words (pinned memory across the bus) and refreshes them.
+// copies are read every time, relaxed (every wave reads them every round; an
+// acquire would invalidate the caches the working waves read from): a wave
+// that acts on a new ticket takes an acquire fence first. At most one wave per
+// kPollTicks reads the host words (pinned memory across the bus) and
+// refreshes them.
 __device__ __forceinline__ void serve_view(const ServeArgs &sv, uint32_t lane, uint64_t &pub, uint32_t &stop) {
     unsigned long long *v = sv.view;
-    stop = uni((uint32_t)__hip_atomic_load(v + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    pub = uni64(__hip_atomic_load(v + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+    stop = uni((uint32_t)__hip_atomic_load(v + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    pub = uni64(__hip_atomic_load(v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t now = uni64(wall_clock64());
     const uint64_t last = uni64(__hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (now - last <= kPollTicks || now < last) return;
@@ -429,10 +440,11 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             serve_view(*sv, lane, pub, stop);
             if (stop >= 2) break;
             if (stop == 1 &&
-                uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) >= pub)
+                uni(__hip_atomic_load(b.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= pub)
                 break;
         } else {
-            const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            // relaxed: leaving needs no data (the launch's end orders the results)
+            const uint32_t dc = uni(__hip_atomic_load(b.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (dc >= b.ncodes) break;
             if (b.cancel) {
                 uint32_t cv = __hip_atomic_load(b.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -443,7 +455,9 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
         uint32_t code = 0;
         uint64_t epoch = 0, tile = 0;
         if (SERVE && ticket != kNoTicket && ticket < pub) {
-            // a new request first: its latency starts at publication
+            // a new request first: its latency starts at publication (the
+            // acquire pairs with the release that published the view's count)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const bool started = serve_start<STATS>(*sv, ticket, lane);
             const uint32_t c = (uint32_t)ticket;
             ticket = kNoTicket;
@@ -458,16 +472,18 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             if (got) code = cur; else cur = kNone;
         }
         if (SERVE) {
-            if (!got && ticket == kNoTicket) {
+            if (!got && ticket == kNoTicket &&
+                uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
+                    pub + kTicketsAhead) {
                 // tickets past the launch's capacity are never published
-                ticket = wave_fetch_add64(b.next_code, 1ull, lane);
+                ticket = wave_fetch_add64_relaxed(b.next_code, 1ull);
                 if (ticket < pub) continue;
             }
         } else {
             // an unstarted code
             while (!got &&
                    uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < b.ncodes) {
-                const unsigned long long nc = wave_fetch_add64(b.next_code, 1ull, lane);
+                const unsigned long long nc = wave_fetch_add64_relaxed(b.next_code, 1ull);
                 if (nc >= b.ncodes) break;
                 if (try_claim(b, (uint32_t)nc, lane, epoch, tile)) {
                     got = true;
@@ -475,23 +491,35 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
                 }
             }
         }
-        if (!got) {
-            // help with a task in the log. Batch: the oldest (throughput).
-            // Server: start at a pseudo-random live entry and walk forward, so
-            // helpers spread over the active tasks (close to processor sharing:
-            // a young request's tasks are not queued behind old large ones).
+        if (!got && !(SERVE && ticket != kNoTicket)) {
+            // Help with a task in the log. Batch: walk from the oldest entry
+            // (throughput). Server: in 7 rounds of 8, start at a pseudo-random
+            // entry among the newest kServeWindow and walk forward, wrapping
+            // inside them: every live task re-enters the log when it starts, so
+            // live entries are recent, while the head can sit behind one long
+            // task with thousands of finished entries after it. Helpers spread
+            // over the active tasks (close to processor sharing). In the other
+            // round a server wave walks from the head, which moves the head past
+            // finished entries.
             const uint64_t head = uni64(__hip_atomic_load(b.log_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             const uint64_t end =
-                uni64(__hip_atomic_load(b.log_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-            uint64_t q = head;
+                uni64(__hip_atomic_load(b.log_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            uint64_t lo = head, off = 0;                          // walk [lo, end) from lo + off
             if (SERVE && end > head + 1) {
                 spread = spread * 6364136223846793005ull + 1442695040888963407ull;   // per-wave LCG
-                const uint64_t live = umin64(end - head, 0xffffffffull);
-                q = head + (((spread >> 32) * live) >> 32);      // in [head, end) without a division
+                if ((spread >> 61) != 0) {
+                    lo = end - umin64(end - head, kServeWindow);
+                    off = (((spread >> 16) & 0xffffffffull) * (end - lo)) >> 32;    // in [0, end - lo)
+                }
             }
-            for (uint32_t steps = 0; steps < 64 && q < end && !got; ++steps, ++q) {
+            const uint64_t range = end > lo ? end - lo : 0;
+            const uint32_t nsteps = (uint32_t)umin64(64, range);
+            for (uint32_t steps = 0; steps < nsteps && !got; ++steps) {
+                const uint64_t q = lo + off;
+                off = (off + 1 == range) ? 0 : off + 1;
+                // relaxed: an entry only names a (code, epoch); try_claim validates it
                 const unsigned long long ent = uni64(
-                    __hip_atomic_load(b.log + (q & (b.log_cap - 1)), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                    __hip_atomic_load(b.log + (q & (b.log_cap - 1)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 if (ent == 0) break;                              // being written
                 const uint32_t cc = (uint32_t)((ent - 1) >> 24);
                 const uint64_t ep = (ent - 1) & ((1ull << 24) - 1);
@@ -508,10 +536,14 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             }
         }
         if (!got) {
-            // exponential back-off (batch: up to ~110 us, serving: ~27 us): idle
-            // waves must not crowd the few cache lines the working waves claim
-            // and complete tiles on
+            // exponential back-off (batch: up to ~110 us, serving: ~27 us, a
+            // ticket holder ~3.4 us): idle waves must not crowd the few cache
+            // lines the working waves claim and complete tiles on
             constexpr uint32_t kMaxShift = SERVE ? 3 : 5;
+            if (SERVE && ticket != kNoTicket) {
+                __builtin_amdgcn_s_sleep(127);
+                continue;
+            }
             const uint32_t rounds = 1u << (idle < kMaxShift ? idle : kMaxShift);
             for (uint32_t r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
             ++idle;

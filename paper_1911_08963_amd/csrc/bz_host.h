@@ -26,10 +26,12 @@ bz_status device_const(int dev, DeviceConst &out);
 
 // Plans of levels 1, 2, ... for one (k, slots): appends one PlanEntry per level
 // (rect_off counted from rect_base + the rects already in `rects`) while
-// C(k, g) < max_comb. Returns the last level planned.
+// C(k, g) < max_comb. Returns the last level planned. With heads_per_tile 0
+// each level gets about target_tiles tiles; max_heads (0 = the planner's own
+// cap) bounds their head steps.
 uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, uint64_t target_tiles,
                            uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
-                           std::vector<Rect> &rects);
+                           std::vector<Rect> &rects, uint32_t max_heads = 0);
 
 // A (Gamma_j, g) task cut into the prefix tasks of one of the paper's
 // schedules (bz_sched.h): entries[lo] tiles the completions of a prefix whose

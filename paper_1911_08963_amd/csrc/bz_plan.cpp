@@ -123,13 +123,20 @@ bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t he
 
 uint32_t build_level_plans(uint32_t k, uint32_t slots, uint32_t heads_per_tile, uint64_t target_tiles,
                            uint64_t max_comb, uint32_t rect_base, std::vector<PlanEntry> &plans,
-                           std::vector<Rect> &rects) {
+                           std::vector<Rect> &rects, uint32_t max_heads) {
     uint32_t gmax = 0;
     for (uint32_t g = 1; g <= std::min<uint32_t>(k, kBinomT); ++g) {
         if (binom_sat(k, g) >= max_comb) break;
+        uint32_t ht = heads_per_tile;
+        if (ht == 0 && max_heads) {
+            // the planner's rule (about target_tiles tiles) with a smaller cap
+            const uint64_t want = binom_sat(k, g) / std::max<uint64_t>(1, target_tiles) / ((uint64_t)kWaveSize * slots);
+            ht = 32;
+            while (ht < max_heads && ht < want) ht <<= 1;
+        }
         LevelPlan p;
         std::string err;
-        if (!plan_level(k, g, slots, heads_per_tile, target_tiles, p, err)) break;
+        if (!plan_level(k, g, slots, ht, target_tiles, p, err)) break;
         PlanEntry e{};
         e.total_tiles = p.total_tiles;
         e.rect_off = rect_base + (uint32_t)rects.size();

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void bz_sched_kernel(SchedArgs s) {
         }
     } else {
         for (;;) {
-            const uint64_t c = wave_fetch_add64(a0.tile_ctr, 1ull, lane);
+            const uint64_t c = wave_fetch_add64_relaxed(a0.tile_ctr, 1ull);   // the task needs no data from the claim
             uint64_t t0 = 0, t1 = 0;
             const uint32_t nt = claim_tasks(s.dist, c, s.ntasks, t0, t1);
             if (nt == 0) break;

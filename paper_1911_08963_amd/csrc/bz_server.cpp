@@ -46,10 +46,12 @@ constexpr uint64_t kLogCap = 1ull << 20;        // shared task log ring
 constexpr size_t kSlotBytes = 32 * 1024;        // staged payload of one request (n <= 256 needs < 25 KiB)
 constexpr uint32_t kEntryAlign = 8;             // plans start on 256-byte boundaries ...
 constexpr uint32_t kRectAlign = 16;             // ... in both tables (16 x 80 B = 5 x 256 B)
-// Head steps per tile of a served request: a tile is at most 64 x 16 x 256
-// sums (about 0.2 ms of one wave), so a newly published request waits little
-// for its ticket holder and a task splits finely between helpers.
-constexpr uint32_t kServeHeads = 256;
+// Tiles of a served request: each level is cut into about target_tiles tiles
+// (by default 4 per wave the device holds, as for bz_min_distance), with at
+// most kServeMaxHeads head steps each: a large task splits into few claims.
+// (The waves that will start new requests hold no tiles meanwhile, so tile
+// length does not delay a request's start.)
+constexpr uint32_t kServeMaxHeads = 4096;
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -245,7 +247,8 @@ bz_status plan_for(bz_server *s, uint32_t k, uint32_t slots, PlanInfo &out, bool
     const uint32_t ro = (s->rects_used + kRectAlign - 1) / kRectAlign * kRectAlign;
     std::vector<bz::PlanEntry> pe;
     std::vector<bz::Rect> rc;
-    const uint32_t gmax = bz::build_level_plans(k, slots, kServeHeads, s->target_tiles, kServeMaxComb, ro, pe, rc);
+    const uint32_t gmax =
+        bz::build_level_plans(k, slots, 0, s->target_tiles, kServeMaxComb, ro, pe, rc, kServeMaxHeads);
     if ((uint64_t)eo + pe.size() > kPlanEntries || (uint64_t)ro + rc.size() > kPlanRects)
         return fail(BZ_ENOMEM, "server plan tables full");
     std::memcpy(s->host_plans + eo, pe.data(), pe.size() * sizeof(bz::PlanEntry));
@@ -305,7 +308,7 @@ bz_status bz_server_create(const bz_server_opts *o, bz_server **out) {
     s->stats = opt.flags & BZ_F_STATS;
     s->slots = opt.slots ? opt.slots : 1024;
     s->stats_cap = opt.stats_cap ? opt.stats_cap : 512;
-    s->target_tiles = opt.target_tiles ? opt.target_tiles : 512;
+    s->target_tiles = opt.target_tiles;     // 0: set from the device below
     s->arena_bytes = opt.arena_bytes ? opt.arena_bytes : ((size_t)1 << 30);
     s->codes_per_launch = opt.codes_per_launch ? opt.codes_per_launch : (1u << 20);
     s->hbm_budget = opt.hbm_budget;
@@ -315,6 +318,7 @@ bz_status bz_server_create(const bz_server_opts *o, bz_server **out) {
     BZ_HIP(hipGetDevice(&s->device));
     bz_status st0 = bz::device_const(s->device, s->dc);
     if (st0 != BZ_OK) return st0;
+    if (!s->target_tiles) s->target_tiles = (uint32_t)s->dc.cus * 32 * bz::kFixedTilesPerWave;
 
     // device memory
     size_t off = 0;

@@ -41,6 +41,28 @@ __device__ __forceinline__ unsigned long long wave_fetch_add64(unsigned long lon
     return uni64(old);
 }
 
+// The same without the fences: for counters whose value carries no data the
+// wave then reads (claims validated by a later acquire, tickets, log slots).
+__device__ __forceinline__ unsigned long long wave_fetch_add64_relaxed(unsigned long long *p, unsigned long long v) {
+    unsigned long long old;
+    uint64_t save;
+    uint32_t first;
+    asm volatile(
+        "s_cmp_eq_u64 exec, 0\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        "s_mov_b64 %1, exec\n\t"
+        "s_ff1_i32_b64 %2, exec\n\t"
+        "s_lshl_b64 exec, 1, %2\n\t"
+        "global_atomic_add_x2 %0, %3, %4, off sc0\n\t"
+        "s_waitcnt vmcnt(0)\n\t"
+        "s_mov_b64 exec, %1\n"
+        "1:"
+        : "=&v"(old), "=&s"(save), "=&s"(first)
+        : "v"(p), "v"(v)
+        : "memory", "scc");
+    return uni64(old);
+}
+
 __device__ __forceinline__ void wave_fetch_max64(unsigned long long *p, unsigned long long v) {
     uint64_t save;
     uint32_t first;
