@@ -225,9 +225,13 @@ __device__ void batch_advance(const BatchArgs &b, const ServeArgs *sv, uint32_t 
         log_append(b, code, epoch + 1, lane);
 }
 
-// Claims one tile of the code's current task: (true, epoch, tile) on success.
+// Claims tiles [tile, tile + count) of the code's current task: one, or for a
+// task of many tiles a few consecutive ones, so that the waves of one large
+// task queue fewer atomics on its cursor and completion words.
+constexpr uint64_t kClaim2 = 16384, kClaim4 = 65536;     // tiles per task from which 2, 4 per claim
 __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uint32_t lane, uint64_t &epoch,
-                                          uint64_t &tile) {
+                                          uint64_t &tile, uint64_t &count) {
+    (void)lane;
     CodeState *S = b.state + code;
     const unsigned long long w0 = uni64(__hip_atomic_load(&S->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t e0 = w0 >> kEpochShift;
@@ -235,19 +239,22 @@ __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uin
     const unsigned long long tw0 =
         uni64(__hip_atomic_load(&S->slot[e0 & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
+    const uint64_t T0 = tw0 & kCursorMask;
+    const uint64_t K = T0 >= kClaim4 ? 4 : (T0 >= kClaim2 ? 2 : 1);
     // relaxed: the acquire load of the slot's tile word below orders what follows
-    const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, 1ull);
+    const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, K);
     const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
     if (e == kDoneEpoch) return false;
     const unsigned long long tw =
         uni64(__hip_atomic_load(&S->slot[e & 1].tiles, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    if ((tw >> kEpochShift) != e || t >= (tw & kCursorMask)) return false;
+    const uint64_t T = tw & kCursorMask;
+    if ((tw >> kEpochShift) != e || t >= T) return false;
     epoch = e;
     tile = t;
+    count = umin64(K, T - t);
     return true;
 }
 
-// Whether a log entry's task can no longer hand out tiles.
 __device__ __forceinline__ bool entry_exhausted(const BatchArgs &b, uint32_t code, uint64_t ep) {
     CodeState *S = b.state + code;
     const unsigned long long w = uni64(__hip_atomic_load(&S->cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -453,7 +460,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
         }
         bool got = false;
         uint32_t code = 0;
-        uint64_t epoch = 0, tile = 0;
+        uint64_t epoch = 0, tile = 0, count = 1;
         if (SERVE && ticket != kNoTicket && ticket < pub) {
             // a new request first: its latency starts at publication (the
             // acquire pairs with the release that published the view's count)
@@ -462,13 +469,13 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             const uint32_t c = (uint32_t)ticket;
             ticket = kNoTicket;
             if (!started) continue;                    // stopping: the loop's top leaves
-            if (try_claim(b, c, lane, epoch, tile)) {
+            if (try_claim(b, c, lane, epoch, tile, count)) {
                 got = true;
                 code = cur = c;
             }
         }
         if (!got && cur != kNone) {
-            got = try_claim(b, cur, lane, epoch, tile);
+            got = try_claim(b, cur, lane, epoch, tile, count);
             if (got) code = cur; else cur = kNone;
         }
         if (SERVE) {
@@ -485,7 +492,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
                    uni64(__hip_atomic_load(b.next_code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < b.ncodes) {
                 const unsigned long long nc = wave_fetch_add64_relaxed(b.next_code, 1ull);
                 if (nc >= b.ncodes) break;
-                if (try_claim(b, (uint32_t)nc, lane, epoch, tile)) {
+                if (try_claim(b, (uint32_t)nc, lane, epoch, tile, count)) {
                     got = true;
                     code = cur = (uint32_t)nc;
                 }
@@ -529,7 +536,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
                         wave_fetch_max64(b.log_head, q + 1);
                     continue;
                 }
-                if (try_claim(b, cc, lane, epoch, tile)) {
+                if (try_claim(b, cc, lane, epoch, tile, count)) {
                     got = true;
                     code = cur = cc;
                 }
@@ -550,11 +557,11 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             continue;
         }
         idle = 0;
-        batch_tile<STATS>(b, code, epoch, tile, lane, binom_c);
+        for (uint64_t i = 0; i < count; ++i) batch_tile<STATS>(b, code, epoch, tile + i, lane, binom_c);
         TaskSlot *s = &b.state[code].slot[epoch & 1];
         const uint64_t T = uni64(s->tiles) & kCursorMask;
-        const unsigned long long prev = wave_fetch_add64(&s->completed, 1ull, lane);
-        if (prev + 1 == T) batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
+        const unsigned long long prev = wave_fetch_add64(&s->completed, count, lane);
+        if (prev + count == T) batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
     }
 }
 
