@@ -228,7 +228,7 @@ __device__ void batch_advance(const BatchArgs &b, const ServeArgs *sv, uint32_t 
 // Claims tiles [tile, tile + count) of the code's current task: one, or for a
 // task of many tiles a few consecutive ones, so that the waves of one large
 // task queue fewer atomics on its cursor and completion words.
-constexpr uint64_t kClaim2 = 16384, kClaim4 = 65536;     // tiles per task from which 2, 4 per claim
+constexpr uint64_t kClaim2 = 4096, kClaim4 = 16384, kClaim8 = 65536;   // tiles per task from which 2, 4, 8 per claim
 __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uint32_t lane, uint64_t &epoch,
                                           uint64_t &tile, uint64_t &count) {
     (void)lane;
@@ -240,7 +240,7 @@ __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uin
         uni64(__hip_atomic_load(&S->slot[e0 & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
     const uint64_t T0 = tw0 & kCursorMask;
-    const uint64_t K = T0 >= kClaim4 ? 4 : (T0 >= kClaim2 ? 2 : 1);
+    const uint64_t K = T0 >= kClaim8 ? 8 : (T0 >= kClaim4 ? 4 : (T0 >= kClaim2 ? 2 : 1));
     // relaxed: the acquire load of the slot's tile word below orders what follows
     const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, K);
     const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
