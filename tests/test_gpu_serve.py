@@ -180,3 +180,39 @@ def test_serving_workload_sample(bz):
     for c, p, m in zip(kept, plain, mix):
         _same(m, p)
         assert bf.in_code(m.witness, c.G, c.n)
+
+
+def _large_serving_codes(bz, count, lo, hi):
+    kept, i = [], 0
+    while len(kept) < count:
+        c = inputs.serve_code(i)
+        i += 1
+        mf, km = bz.prepare_host(c.G, c.n)[1:3]
+        if lo <= workloads.estimated_cost(c.n, c.k, mf, km) <= hi:
+            kept.append(c)
+    return kept
+
+
+def test_large_requests(bz):
+    """Requests of 2e10-1e11 combinations, whose large tasks have thousands of tiles (claimed
+    2, 4 or 8 at a time): statistics equal the plain search's, alone and mixed."""
+    kept = _large_serving_codes(bz, 6, 2e10, 1e11)
+    _say("large requests:", [(c.n, c.k) for c in kept])
+    plain = _plain(bz, [(c.G, c.n) for c in kept], stats=True)
+    hcodes = [bz.Code(c.G, c.n, host_only=True) for c in kept]
+    with bz.Server(slots=16, stats=True) as srv:
+        alone = [srv.wait(srv.submit(h)) for h in hcodes]
+        mix = _run_mix(srv, hcodes)
+    for c, p, a, m in zip(kept, plain, alone, mix):
+        _same(a, p)
+        _same(m, p)
+        assert bf.in_code(m.witness, c.G, c.n) and bf.in_code(a.witness, c.G, c.n)
+    # the batched search with as many tiles per task (multi-tile claims there too)
+    objs = [bz.Code(c.G, c.n) for c in kept]
+    outs, sts = bz.min_distance_batch(objs, stats=True, tiles_per_task=16384)
+    for c, p, o, st in zip(kept, plain, outs, sts):
+        assert st == 0
+        _same(o, p)
+        assert bf.in_code(o.witness, c.G, c.n)
+    for o in objs:
+        o.close()
