@@ -108,7 +108,7 @@ struct BatchLayout {
     uint32_t done_init = 0, grid = 0, stats_total = 0;
     uint64_t log_cap = 0;
     size_t off_codes = 0, off_states = 0, off_plans = 0, off_rects = 0, off_stats = 0,
-           off_recover = 0, off_log = 0, off_done = 0, total = 0;
+           off_recover = 0, off_log = 0, off_done = 0, off_args = 0, total = 0;
 };
 
 bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt, int cus, bool stats,
@@ -183,6 +183,7 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
     Lo.log_cap = cap2;
     Lo.off_log = off; off = align256(off + (Lo.log_cap + 3) * sizeof(unsigned long long));
     Lo.off_done = off; off = align256(off + sizeof(uint32_t));
+    Lo.off_args = off; off = align256(off + sizeof(bz::BatchArgs));
     Lo.total = std::max(off, kWsBytes);
     return BZ_OK;
 }
@@ -271,6 +272,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     b.done_count = (unsigned int *)(ws + Lo.off_done);
     b.cancel = (const uint32_t *)opt.cancel;
     b.ncodes = count;
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_args, &b, sizeof(b), hipMemcpyHostToDevice, st));
 
     // one captured graph: the persistent search, then witness recovery
     hipStream_t cs = nullptr;
@@ -294,7 +296,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     BZ_HIP(hipEventRecord(e_ready, st));
     BZ_HIP(hipStreamWaitEvent(cs, e_ready, 0));
     BZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t le = bz::launch_batch(b, Lo.grid, stats, cs);
+    hipError_t le = bz::launch_batch((const bz::BatchArgs *)(ws + Lo.off_args), Lo.grid, stats, cs);
     hipError_t lr = (le == hipSuccess && !(opt.flags & BZ_F_NO_WITNESS)) ? bz::launch_batch_recover(b, cs) : hipSuccess;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess || lr != hipSuccess || ec != hipSuccess)

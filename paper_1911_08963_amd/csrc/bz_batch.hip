@@ -565,13 +565,14 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
     }
 }
 
+// The arguments of both persistent kernels live in device memory: passed by
+// value, their address (taken by the rare paths) would force a copy into
+// per-lane scratch.
 template <bool STATS>
-__global__ __launch_bounds__(kBlock) void bz_batch_kernel(BatchArgs b) {
-    queue_loop<STATS, false>(b, nullptr);
+__global__ __launch_bounds__(kBlock) void bz_batch_kernel(const BatchArgs *__restrict__ b) {
+    queue_loop<STATS, false>(*b, nullptr);
 }
 
-// The arguments live in device memory: passed by value, their address
-// (taken by the rare paths) would force a copy into per-lane scratch.
 template <bool STATS>
 __global__ __launch_bounds__(kBlock) void bz_serve_kernel(const ServeArgs *__restrict__ sv) {
     queue_loop<STATS, true>(sv->b, sv);
@@ -747,12 +748,12 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
 }
 
 template <bool STATS>
-static hipError_t launch_batch_t(const BatchArgs &b, uint32_t grid, hipStream_t st) {
+static hipError_t launch_batch_t(const BatchArgs *b, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL((bz_batch_kernel<STATS>), dim3(grid), dim3(kBlock), 0, st, b);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st) {
+hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, hipStream_t st) {
     return stats ? launch_batch_t<true>(b, grid, st) : launch_batch_t<false>(b, grid, st);
 }
 

@@ -175,7 +175,8 @@ struct ServeArgs {
 hipError_t launch_serve(const ServeArgs *sv, uint32_t grid, bool stats, hipStream_t st);
 int serve_blocks_per_cu(bool stats);
 
-hipError_t launch_batch(const BatchArgs &b, uint32_t grid, bool stats, hipStream_t st);
+// b: the arguments in device memory (read while the kernel runs).
+hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, hipStream_t st);
 hipError_t launch_batch_recover(const BatchArgs &b, hipStream_t st);
 int batch_blocks_per_cu(bool stats);
 
