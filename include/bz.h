@@ -139,8 +139,10 @@ typedef struct {
  * prefix size; S_* take it relative to g (the prefix has g - p elements).
  * A prefix of g or more elements, or of none, makes the level one task. The
  * result (d, bounds, statistics) is the same under every schedule; only the
- * time changes. Schedules 1..8 need prefix >= 1, allocate their tilings on the
- * device per search, and apply to bz_min_distance only (the batch call returns
+ * time changes. Schedules 1..8 need prefix >= 1, use the fixed lane sums per
+ * lane (16 up to W = 4, else 8) and tilings of their own (slots_per_lane and
+ * heads_per_tile are ignored), allocate those tilings on the device per
+ * search, and apply to bz_min_distance only (the batch call returns
  * BZ_EINVAL; the server ignores the field). */
 enum {
     BZ_SCHED_TILES = 0,
