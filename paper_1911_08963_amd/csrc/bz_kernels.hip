@@ -8,7 +8,9 @@
 // by uniform arithmetic (tiles of a level cost the same, so no work queue is
 // needed inside one task). Before each tile a wave reads the task key and
 // stops when the upper bound has reached the certified lower bound (fast mode
-// only) or when the caller's cancel word is set.
+// only) or when the caller's cancel word is set. A wave keeps its combination
+// count and statistics word in LDS and adds them to the task's words once,
+// when it leaves.
 #include <hip/hip_runtime.h>
 
 #include "bz_internal.h"
@@ -18,7 +20,7 @@
 namespace bz {
 
 template <int W, int SLOTS, bool PARTIAL, bool STATS>
-__global__ __launch_bounds__(kBlock) void bz_enum_kernel(TaskArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS || PARTIAL) ? 1 : 5))) void bz_enum_kernel(TaskArgs a) {
     extern __shared__ uint64_t smem[];
     const uint32_t bt = a.g + 1;                          // binomial row stride in LDS
     uint64_t *sbin = smem;                                // (k+1) x (g+1)
@@ -40,6 +42,18 @@ __global__ __launch_bounds__(kBlock) void bz_enum_kernel(TaskArgs a) {
     const uint32_t waves_per_block = blockDim.x / kWaveSize;
     const uint64_t first = (uint64_t)blockIdx.x * waves_per_block + uni(threadIdx.x / kWaveSize);
     const uint64_t stride = (uint64_t)gridDim.x * waves_per_block;
+    // The wave's combination count and statistics word live in LDS until it
+    // leaves: one global atomic per wave instead of one per tile on the same
+    // word (on a level of many short tiles those serialise the whole launch).
+    __shared__ unsigned long long wave_words[kBlock / kWaveSize][2];
+    const uint32_t wv = uni(threadIdx.x / kWaveSize);
+    if (lane == 0) {
+        wave_words[wv][0] = 0;
+        wave_words[wv][1] = ~0ull;                       // "none", as the task's own word starts
+    }
+    TaskArgs t = a;
+    t.ncomb = &wave_words[wv][0];
+    t.stats = &wave_words[wv][1];
     for (uint64_t it = first; it < a.total_tiles; it += stride) {
         const uint64_t tile = uni64(it);
         bool stop = false;
@@ -53,7 +67,14 @@ __global__ __launch_bounds__(kBlock) void bz_enum_kernel(TaskArgs a) {
             stop = stop || uni(cv) != 0u;
         }
         if (stop) break;
-        run_tile<W, SLOTS, PARTIAL, STATS>(a, rows, binom_c, srow, sbin, bt, rect_p, tile, lane);
+        run_tile<W, SLOTS, PARTIAL, STATS>(t, rows, binom_c, srow, sbin, bt, rect_p, tile, lane);
+    }
+    if (lane == 0 && wave_words[wv][0]) {
+        atomicAdd(a.ncomb, wave_words[wv][0]);
+        if (STATS) {
+            const unsigned long long sw = wave_words[wv][1];
+            stats_merge(a.stats, (uint32_t)(sw >> kCountBits), sw & kCountMask);
+        }
     }
 }
 
