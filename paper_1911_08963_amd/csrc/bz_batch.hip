@@ -63,9 +63,12 @@ __device__ __forceinline__ uint32_t certified_bound(uint32_t j, uint32_t g, uint
     return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)(e > 0 ? e : 0);
 }
 
+// One tile of a code's current task. The tile's combination count and
+// statistics go to the wave's own words (LDS), which the caller adds to the
+// task's once per claim.
 template <bool STATS>
 __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, uint64_t epoch, uint64_t tile,
-                                           uint32_t lane, cptr64 binom_c) {
+                                           uint32_t lane, cptr64 binom_c, unsigned long long *wave_words) {
     const BatchCode &D = b.codes[code];
     TaskSlot *s = &b.state[code].slot[epoch & 1];
     const uint32_t j = uni(s->j), g = uni(s->g);
@@ -79,8 +82,8 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     a.binom = b.binom;
     a.rects = b.rects + uni(s->rect_off);
     a.key = &s->key;
-    a.stats = &s->stats;
-    a.ncomb = &s->ncomb;
+    a.ncomb = wave_words;
+    a.stats = wave_words + 1;
     a.nrects = uni(s->nrects);
     a.k = k;
     a.k_low = partial ? uni(D.k_m) : k;
@@ -440,6 +443,8 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
     uint32_t idle = 0;                                 // consecutive rounds without work
     uint64_t ticket = kNoTicket;                       // serving: the request this wave will start
     uint64_t spread = uni64(((uint64_t)blockIdx.x << 8) ^ (threadIdx.x >> 6) ^ 0x9e3779b97f4a7c15ull);
+    __shared__ unsigned long long wave_words[kBlock / kWaveSize][2];   // per wave: combinations, statistics
+    const uint32_t wv = uni(threadIdx.x / kWaveSize);
     for (;;) {
         uint64_t pub = 0;
         if (SERVE) {
@@ -557,8 +562,22 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             continue;
         }
         idle = 0;
-        for (uint64_t i = 0; i < count; ++i) batch_tile<STATS>(b, code, epoch, tile + i, lane, binom_c);
+        // the claim's count and statistics: the wave's LDS words, then one
+        // atomic each on the task's words before the completion count
+        if (lane == 0) {
+            wave_words[wv][0] = 0;
+            wave_words[wv][1] = ~0ull;
+        }
+        for (uint64_t i = 0; i < count; ++i)
+            batch_tile<STATS>(b, code, epoch, tile + i, lane, binom_c, wave_words[wv]);
         TaskSlot *s = &b.state[code].slot[epoch & 1];
+        if (lane == 0 && wave_words[wv][0]) {
+            atomicAdd(&s->ncomb, wave_words[wv][0]);
+            if (STATS) {
+                const unsigned long long sw = wave_words[wv][1];
+                stats_merge(&s->stats, (uint32_t)(sw >> kCountBits), sw & kCountMask);
+            }
+        }
         const uint64_t T = uni64(s->tiles) & kCursorMask;
         const unsigned long long prev = wave_fetch_add64(&s->completed, count, lane);
         if (prev + count == T) batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
@@ -569,7 +588,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
 // value, their address (taken by the rare paths) would force a copy into
 // per-lane scratch.
 template <bool STATS>
-__global__ __launch_bounds__(kBlock) void bz_batch_kernel(const BatchArgs *__restrict__ b) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bz_batch_kernel(const BatchArgs *__restrict__ b) {
     queue_loop<STATS, false>(*b, nullptr);
 }
 
