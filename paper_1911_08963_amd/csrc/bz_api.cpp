@@ -573,7 +573,10 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
             const uint32_t W = c->W(j);
             uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
             uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
-            if (!opt.slots_per_lane && !opt.heads_per_tile) (void)bz::tuned_choice(W, slots, per_wave);
+            if (!opt.slots_per_lane && !opt.heads_per_tile) {
+                (void)bz::tuned_choice(W, slots, per_wave);
+                if ((double)bz::binom_sat(k, g) < bz::kLargeLevelComb) per_wave = 1;
+            }
             if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
             if (use_sched) slots = bz::slots_for_w(W);      // the schedule kernel's fixed lane sums
             const bz::LevelPlan *plan = nullptr;

@@ -32,6 +32,10 @@ constexpr uint32_t slots_for_w(uint32_t W) { return W <= 4 ? 16u : 8u; }
 // search: enough for the static round-robin to balance, few enough that a
 // tile's setup (unranking its lane subsets) stays small against its work.
 constexpr uint32_t kFixedTilesPerWave = 4;
+// Levels of fewer sums than this (the size the autotuner times) get one tile
+// per resident wave: there a tile's setup weighs more than the balance that
+// smaller tiles buy.
+constexpr double kLargeLevelComb = 2e10;
 
 // One product of two colex subset spaces inside the g-subsets of [0, k):
 // every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a

@@ -31,7 +31,7 @@ std::mutex g_tune_mu;
 std::map<uint32_t, bz_tune_entry> g_tuned;    // W -> chosen (slots, tiles per wave)
 uint32_t g_batch_tiles = 0;                   // tiles per task for batches (0 = not tuned)
 
-constexpr double kTuneCombinations = 2e10;    // size of the timed task (several milliseconds)
+constexpr double kTuneCombinations = bz::kLargeLevelComb;    // size of the timed task (several milliseconds)
 constexpr uint32_t kTilesPerWave[] = {1, 2, 4, 8, 16, 64};    // kFixedTilesPerWave: the fixed rule
 
 uint64_t splitmix(uint64_t &s) {
