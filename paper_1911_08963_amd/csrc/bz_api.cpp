@@ -82,6 +82,34 @@ uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t 
     return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)std::max<int64_t>(0, extra);
 }
 
+// Pinned host words for the per-task read-back of a search (a copy into
+// pageable memory goes through a staging buffer). Buffers are taken from and
+// returned to a process-wide pool and kept until the process ends.
+class PinnedWords {
+  public:
+    PinnedWords() {
+        std::lock_guard<std::mutex> lk(mu());
+        if (!pool().empty()) {
+            p_ = pool().back();
+            pool().pop_back();
+        } else if (hipHostMalloc((void **)&p_, 64, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p_ = nullptr;
+        }
+    }
+    ~PinnedWords() {
+        if (!p_) return;
+        std::lock_guard<std::mutex> lk(mu());
+        pool().push_back(p_);
+    }
+    unsigned long long *get(unsigned long long *fallback) { return p_ ? p_ : fallback; }
+
+  private:
+    static std::mutex &mu() { static std::mutex m; return m; }
+    static std::vector<unsigned long long *> &pool() { static std::vector<unsigned long long *> v; return v; }
+    unsigned long long *p_ = nullptr;
+};
+
 struct Best {
     bool have = false;
     uint32_t j = 0, g = 0, slots = 0, ht = 0;
@@ -557,6 +585,14 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     }
 
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots, tiles/wave) -> plan
+    // Tilings already on the device (rect offset in the workspace): a level's
+    // tiling is uploaded once for all its Gamma_j. When the region is full it
+    // starts over; every earlier launch has finished by then.
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, size_t> on_device;
+    size_t rects_used = 0;
+    PinnedWords pinned;
+    unsigned long long stack_words[3];
+    unsigned long long *words = pinned.get(stack_words);
     std::map<std::pair<uint32_t, uint32_t>, bz::SchedPlan> splans;            // (g, slots) -> prefix tasks
     struct DevBuf {
         char *p = nullptr;
@@ -638,9 +674,18 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                     plans[key] = std::move(p);
                 }
                 plan = &plans[key];
-                BZ_HIP(hipMemcpyAsync(d_rects, plan->rects.data(), plan->rects.size() * sizeof(bz::Rect),
-                                      hipMemcpyHostToDevice, st));
-                a.rects = d_rects;
+                auto od = on_device.find(key);
+                if (od == on_device.end()) {
+                    if (rects_used + plan->rects.size() > kMaxRects) {
+                        on_device.clear();
+                        rects_used = 0;
+                    }
+                    BZ_HIP(hipMemcpyAsync(d_rects + rects_used, plan->rects.data(),
+                                          plan->rects.size() * sizeof(bz::Rect), hipMemcpyHostToDevice, st));
+                    od = on_device.emplace(key, rects_used).first;
+                    rects_used += plan->rects.size();
+                }
+                a.rects = d_rects + od->second;
                 a.nrects = (uint32_t)plan->rects.size();
                 a.heads_per_tile = plan->heads_per_tile;
                 a.total_tiles = plan->total_tiles;
@@ -650,8 +695,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
                 BZ_HIP(hipEventRecord(ev1, st));
             }
-            unsigned long long words[3];
-            BZ_HIP(hipMemcpyAsync(words, d_key, sizeof(words), hipMemcpyDeviceToHost, st));
+            BZ_HIP(hipMemcpyAsync(words, d_key, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
             BZ_HIP(hipStreamSynchronize(st));
             float ms = 0.f;
             BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
