@@ -244,12 +244,15 @@ __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uin
     if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
     const uint64_t T0 = tw0 & kCursorMask;
     const uint64_t K = T0 >= kClaim8 ? 8 : (T0 >= kClaim4 ? 4 : (T0 >= kClaim2 ? 2 : 1));
-    // relaxed: the acquire load of the slot's tile word below orders what follows
+    // acquire without release: the fence after the fetch-add pairs with the
+    // release store that published this epoch (the task's slot is written
+    // before it), and the wave publishes nothing by claiming
     const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, K);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
     if (e == kDoneEpoch) return false;
     const unsigned long long tw =
-        uni64(__hip_atomic_load(&S->slot[e & 1].tiles, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        uni64(__hip_atomic_load(&S->slot[e & 1].tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t T = tw & kCursorMask;
     if ((tw >> kEpochShift) != e || t >= T) return false;
     epoch = e;
