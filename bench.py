@@ -364,7 +364,31 @@ def main():
     if not args.no_cpu:
         v1, n1, r1, t1 = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds)
         vp, np_, rp, tp = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds, pool, nprocs)
+        # the oracle's own time-to-d: plain40 on one core, plain128 on the pool,
+        # plain192's full run as cached with the golden file
+        import oracle
+        from oracle import parallel
+        import statistics
+        c40 = inputs.plain_code("plain40")
+        t40 = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            oracle.min_distance(c40.G, c40.n)
+            t40.append(time.perf_counter() - t0)
+        c128 = inputs.plain_code("plain128")
+        t0 = time.perf_counter()
+        r128 = parallel.min_distance_parallel(c128.G, c128.n, nprocs=nprocs, pool=pool)
+        t128 = time.perf_counter() - t0
         pool.close()
+        with open(os.path.join(ROOT, "tests", "golden", "plain192_oracle.json")) as fh:
+            g192 = json.load(fh)
+        oracle_ttd = {
+            "plain40": {"seconds": statistics.median(t40), "cores": 1, "runs": 20},
+            "plain128": {"seconds": t128, "cores": nprocs, "d": r128["d"]},
+            "plain192": {"seconds": g192["oracle_seconds"], "cores": g192["nprocs"],
+                         "note": "the full run cached with tests/golden/plain192_oracle.json, "
+                                 "measured once on the build machine, not this host"},
+        }
         line["cpu_baseline"] = {
             "value": vp, "unit": "combinations/s", "cores": nprocs, "kind": "oracle",
             "sample": f"C oracle on the same code, levels 1-{args.cpu_max_level} of all 3 Gamma_j, "
@@ -373,6 +397,7 @@ def main():
             "single_core": {"value": v1, "cores": 1,
                             "sample": f"the same levels single-threaded, {r1} repetitions ({n1} combinations "
                                       f"in {t1:.1f} s)"},
+            "time_to_d_s": oracle_ttd,
         }
     print(json.dumps(line), flush=True)
 
