@@ -205,7 +205,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the search shards by "
-              "combination rank ranges across GPUs, which this build does not run.", file=sys.stderr)
+              "combination rank ranges across GPUs, which this library does not do.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
