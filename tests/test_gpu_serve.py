@@ -216,3 +216,18 @@ def test_large_requests(bz):
         assert bf.in_code(o.witness, c.G, c.n)
     for o in objs:
         o.close()
+
+
+def test_burst_of_requests(bz):
+    """1000 requests of the serving distribution (estimated cost <= 1e9) submitted as one burst,
+    up to 1024 in flight: every statistics-mode result equals the plain search's."""
+    info = lambda c: bz.prepare_host(c.G, c.n)[1:3]
+    kept, drawn, est = workloads.select(lambda i: inputs.serve_code(i, base_seed=5_000_000), info, 1000, 1e9)
+    _say("burst:", len(kept), "requests of", drawn, "drawn; est. combinations", f"{sum(est):.3g}")
+    hcodes = [bz.Code(c.G, c.n, host_only=True) for c in kept]
+    with bz.Server(slots=1024, stats=True) as srv:
+        mix = _run_mix(srv, hcodes, timeout=240.0)
+    plain = _plain(bz, [(c.G, c.n) for c in kept], stats=True)
+    for c, p, m in zip(kept, plain, mix):
+        _same(m, p)
+        assert m.status == 0 and bf.in_code(m.witness, c.G, c.n)
