@@ -289,7 +289,7 @@ typedef struct {
     uint32_t stats_cap;         /* task records kept per request (0 = 512)                         */
     uint32_t target_tiles;      /* tiles per task aimed at by the planner (0 = 4 per resident wave) */
     size_t arena_bytes;         /* device bytes for Gamma_j of one kernel launch (0 = 1 GiB)       */
-    uint32_t codes_per_launch;  /* requests per kernel launch before a relaunch (0 = 1 << 20)      */
+    uint32_t codes_per_launch;  /* requests per kernel launch before a relaunch (0 = 1 << 18)      */
     uint32_t _reserved;
 } bz_server_opts;
 

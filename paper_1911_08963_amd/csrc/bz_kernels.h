@@ -65,28 +65,37 @@ struct alignas(64) BatchCode {
 static_assert(sizeof(BatchCode) % 64 == 0, "BatchCode fills whole cache lines");
 
 // One task of one code; two per code, selected by the parity of the epoch.
-struct alignas(64) TaskSlot {
-    unsigned long long key;       // (min weight << 55) | tile
-    unsigned long long stats;     // (min << 55) | count
-    unsigned long long ncomb;     // combinations enumerated
+// The words of a task that many waves touch each sit on a 128-byte line of
+// their own (the L2 serialises atomics per line): the completion count with
+// the counts added once per claim, the key every tile polls, and the
+// read-mostly description of the task.
+struct alignas(128) TaskSlot {
     unsigned long long completed; // tiles finished
+    unsigned long long ncomb;     // combinations enumerated
+    unsigned long long stats;     // (min << 55) | count
+    unsigned long long _line0[13];
+    unsigned long long key;       // (min weight << 55) | tile
+    unsigned long long _line1[15];
     unsigned long long tiles;     // (epoch << 40) | tile count: which task this slot holds
     uint32_t j, g, rect_off, nrects, heads_per_tile, exit_at;
     uint32_t u_prev, _pad[3];
 };
+static_assert(sizeof(TaskSlot) == 384, "TaskSlot is three 128-byte lines");
 
 constexpr uint64_t kEpochShift = 40;
 constexpr uint64_t kCursorMask = (1ull << kEpochShift) - 1;
 constexpr uint64_t kDoneEpoch = (1ull << 24) - 1;
 
-struct alignas(64) CodeState {
+struct alignas(128) CodeState {
     unsigned long long cursor;    // (epoch << 40) | next tile to hand out; epoch kDoneEpoch = finished
+    unsigned long long _line0[15];   // the claim cursor has its line to itself
     uint32_t U, L, Lcert, status;
     uint32_t last_level, nstats, have_best, best_j;
     uint32_t best_g, _pad0;
     uint64_t best_tile, combinations;
     TaskSlot slot[2];
 };
+static_assert(sizeof(CodeState) == 1024, "CodeState is eight 128-byte lines");
 
 struct BatchStat {                // one completed task
     uint16_t matrix, level;

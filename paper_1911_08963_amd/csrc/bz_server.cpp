@@ -310,7 +310,7 @@ bz_status bz_server_create(const bz_server_opts *o, bz_server **out) {
     s->stats_cap = opt.stats_cap ? opt.stats_cap : 512;
     s->target_tiles = opt.target_tiles;     // 0: set from the device below
     s->arena_bytes = opt.arena_bytes ? opt.arena_bytes : ((size_t)1 << 30);
-    s->codes_per_launch = opt.codes_per_launch ? opt.codes_per_launch : (1u << 20);
+    s->codes_per_launch = opt.codes_per_launch ? opt.codes_per_launch : (1u << 18);
     s->hbm_budget = opt.hbm_budget;
     s->ring = 1024;                          // a power of two, at least 4 x slots
     while (s->ring < 4ull * s->slots) s->ring <<= 1;
