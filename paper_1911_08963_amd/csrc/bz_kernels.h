@@ -66,21 +66,22 @@ static_assert(sizeof(BatchCode) % 64 == 0, "BatchCode fills whole cache lines");
 
 // One task of one code; two per code, selected by the parity of the epoch.
 // The words of a task that many waves touch each sit on a 128-byte line of
-// their own (the L2 serialises atomics per line): the completion count with
-// the counts added once per claim, the key every tile polls, and the
-// read-mostly description of the task.
+// their own (the L2 serialises atomics per line): the completion count, the
+// counts added once per claim, the key every tile polls, and the read-mostly
+// description of the task.
 struct alignas(128) TaskSlot {
     unsigned long long completed; // tiles finished
+    unsigned long long _line0[15];
     unsigned long long ncomb;     // combinations enumerated
     unsigned long long stats;     // (min << 55) | count
-    unsigned long long _line0[13];
+    unsigned long long _line1[14];
     unsigned long long key;       // (min weight << 55) | tile
-    unsigned long long _line1[15];
+    unsigned long long _line2[15];
     unsigned long long tiles;     // (epoch << 40) | tile count: which task this slot holds
     uint32_t j, g, rect_off, nrects, heads_per_tile, exit_at;
     uint32_t u_prev, _pad[3];
 };
-static_assert(sizeof(TaskSlot) == 384, "TaskSlot is three 128-byte lines");
+static_assert(sizeof(TaskSlot) == 512, "TaskSlot is four 128-byte lines");
 
 constexpr uint64_t kEpochShift = 40;
 constexpr uint64_t kCursorMask = (1ull << kEpochShift) - 1;
@@ -95,7 +96,7 @@ struct alignas(128) CodeState {
     uint64_t best_tile, combinations;
     TaskSlot slot[2];
 };
-static_assert(sizeof(CodeState) == 1024, "CodeState is eight 128-byte lines");
+static_assert(sizeof(CodeState) == 1280, "CodeState is ten 128-byte lines");
 
 struct BatchStat {                // one completed task
     uint16_t matrix, level;
