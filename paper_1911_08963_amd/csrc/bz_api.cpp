@@ -132,7 +132,7 @@ struct BatchLayout {
     std::vector<bz::PlanEntry> plans;
     std::vector<bz::Rect> rects;
     std::vector<unsigned long long> log_init;   // initial task-log entries
-    unsigned long long log_ht[3] = {0, 0, 0};    // initial log head, log tail, next code
+    unsigned long long log_tail = 0;             // initial log tail (head and next code start at 0)
     uint32_t done_init = 0, grid = 0, stats_total = 0;
     uint64_t log_cap = 0;
     size_t off_codes = 0, off_states = 0, off_plans = 0, off_rects = 0, off_stats = 0,
@@ -209,7 +209,7 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
     uint64_t cap2 = 1;
     while (cap2 < Lo.log_cap) cap2 <<= 1;
     Lo.log_cap = cap2;
-    Lo.off_log = off; off = align256(off + (Lo.log_cap + 3) * sizeof(unsigned long long));
+    Lo.off_log = off; off = align256(off + (Lo.log_cap + bz::kLogEntries) * sizeof(unsigned long long));
     Lo.off_done = off; off = align256(off + sizeof(uint32_t));
     Lo.off_args = off; off = align256(off + sizeof(bz::BatchArgs));
     Lo.total = std::max(off, kWsBytes);
@@ -276,12 +276,13 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     BZ_HIP(hipMemcpyAsync(ws + Lo.off_rects, Lo.rects.data(), Lo.rects.size() * sizeof(bz::Rect), hipMemcpyHostToDevice, st));
     BZ_HIP(hipMemcpyAsync(ws + Lo.off_done, &done_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
     BZ_HIP(hipMemsetAsync(ws + Lo.off_recover, 0, count * sizeof(bz::BatchRecover), st));
-    // task log: [head, tail, entries...]
-    BZ_HIP(hipMemsetAsync(ws + Lo.off_log, 0, (Lo.log_cap + 3) * sizeof(unsigned long long), st));
-    Lo.log_ht[1] = Lo.log_init.size();
-    BZ_HIP(hipMemcpyAsync(ws + Lo.off_log, Lo.log_ht, sizeof(Lo.log_ht), hipMemcpyHostToDevice, st));
+    // task log: control words (head 0, tail = the initial entries, next code 0), then entries
+    BZ_HIP(hipMemsetAsync(ws + Lo.off_log, 0, (Lo.log_cap + bz::kLogEntries) * sizeof(unsigned long long), st));
+    Lo.log_tail = Lo.log_init.size();
+    BZ_HIP(hipMemcpyAsync(ws + Lo.off_log + bz::kLogTail * sizeof(unsigned long long), &Lo.log_tail,
+                          sizeof(Lo.log_tail), hipMemcpyHostToDevice, st));
     if (!Lo.log_init.empty())
-        BZ_HIP(hipMemcpyAsync(ws + Lo.off_log + 3 * sizeof(unsigned long long), Lo.log_init.data(),
+        BZ_HIP(hipMemcpyAsync(ws + Lo.off_log + bz::kLogEntries * sizeof(unsigned long long), Lo.log_init.data(),
                               Lo.log_init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
 
     bz::BatchArgs b{};
@@ -292,10 +293,11 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     b.binom = dc.binom;
     b.stats = (bz::BatchStat *)(ws + Lo.off_stats);
     b.recover = (bz::BatchRecover *)(ws + Lo.off_recover);
-    b.log_head = (unsigned long long *)(ws + Lo.off_log);
-    b.log_tail = b.log_head + 1;
-    b.next_code = b.log_head + 2;
-    b.log = b.log_head + 3;
+    unsigned long long *log_base = (unsigned long long *)(ws + Lo.off_log);
+    b.log_head = log_base + bz::kLogHead;
+    b.log_tail = log_base + bz::kLogTail;
+    b.next_code = log_base + bz::kLogNext;
+    b.log = log_base + bz::kLogEntries;
     b.log_cap = Lo.log_cap;
     b.done_count = (unsigned int *)(ws + Lo.off_done);
     b.cancel = (const uint32_t *)opt.cancel;

@@ -83,6 +83,11 @@ struct alignas(128) TaskSlot {
 };
 static_assert(sizeof(TaskSlot) == 512, "TaskSlot is four 128-byte lines");
 
+// The task log's control words (head, tail, the next unstarted code or
+// ticket), each on a 128-byte line of its own, then the entries; offsets in
+// 64-bit words from the log's base.
+constexpr size_t kLogHead = 0, kLogTail = 16, kLogNext = 32, kLogEntries = 48;
+
 constexpr uint64_t kEpochShift = 40;
 constexpr uint64_t kCursorMask = (1ull << kEpochShift) - 1;
 constexpr uint64_t kDoneEpoch = (1ull << 24) - 1;

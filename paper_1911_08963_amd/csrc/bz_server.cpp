@@ -156,10 +156,11 @@ bz::ServeArgs serve_args(bz_server *s) {
     b.binom = s->dc.binom;
     b.stats = (bz::BatchStat *)(s->dmem + s->off_stats);
     b.recover = nullptr;
-    b.log_head = (unsigned long long *)(s->dmem + s->off_log);
-    b.log_tail = b.log_head + 1;
-    b.next_code = b.log_head + 2;
-    b.log = b.log_head + 3;
+    unsigned long long *log_base = (unsigned long long *)(s->dmem + s->off_log);
+    b.log_head = log_base + bz::kLogHead;
+    b.log_tail = log_base + bz::kLogTail;
+    b.next_code = log_base + bz::kLogNext;
+    b.log = log_base + bz::kLogEntries;
     b.log_cap = kLogCap;
     b.done_count = (unsigned int *)(s->dmem + s->off_done);
     b.cancel = nullptr;
@@ -181,7 +182,8 @@ bz::ServeArgs serve_args(bz_server *s) {
 
 // Starts a kernel launch with empty counters. Caller holds mu; no kernel runs.
 bz_status launch_locked(bz_server *s) {
-    BZ_HIP(hipMemsetAsync(s->dmem + s->off_log, 0, (kLogCap + 3) * sizeof(unsigned long long), s->stream));
+    BZ_HIP(hipMemsetAsync(s->dmem + s->off_log, 0, (kLogCap + bz::kLogEntries) * sizeof(unsigned long long),
+                          s->stream));
     BZ_HIP(hipMemsetAsync(s->dmem + s->off_done, 0, 256, s->stream));
     BZ_HIP(hipMemsetAsync(s->dmem + s->off_view, 0, 256, s->stream));
     BZ_HIP(hipStreamSynchronize(s->stream));
@@ -327,7 +329,7 @@ bz_status bz_server_create(const bz_server_opts *o, bz_server **out) {
     s->off_plans = off; off = a256(off + (size_t)kPlanEntries * sizeof(bz::PlanEntry));
     s->off_rects = off; off = a256(off + (size_t)kPlanRects * sizeof(bz::Rect));
     s->off_stats = off; off = a256(off + (size_t)s->slots * s->stats_cap * sizeof(bz::BatchStat));
-    s->off_log = off; off = a256(off + (kLogCap + 3) * sizeof(unsigned long long));
+    s->off_log = off; off = a256(off + (kLogCap + bz::kLogEntries) * sizeof(unsigned long long));
     s->off_done = off; off = a256(off + 256);
     s->off_view = off; off = a256(off + 256);
     s->off_ready = off; off = a256(off + kMaxPlans * sizeof(unsigned int));
