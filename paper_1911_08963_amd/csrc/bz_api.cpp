@@ -60,11 +60,16 @@ using bz::fail;
 using bz::g_err;
 using bz::now_s;
 
-// Workspace layout of one search (bytes).
-constexpr size_t kWsTask = 0;          // key, stats, ncomb, tile counter (u64 each)
-constexpr size_t kWsRecover = 64;      // flag, len (u32), codeword (4 x u64)
-constexpr size_t kWsIndices = 128;     // up to 256 u32 row indices
-constexpr size_t kWsRecoverRect = 1280;
+// Workspace layout of one search (bytes). The words many waves touch each get
+// a 128-byte line: the key every tile polls, the statistics and combination
+// count (added once per wave), the schedules' claim counter.
+constexpr size_t kWsKey = 0;           // (min weight << 55) | tile
+constexpr size_t kWsCounts = 128;      // statistics word, then the combination count
+constexpr size_t kWsCtr = 256;         // claim counter of the queue schedules
+constexpr size_t kWsReadBack = 144;    // bytes [0, 144): the key, then (at 128) the two counts
+constexpr size_t kWsRecover = 384;     // flag, len (u32), codeword (4 x u64)
+constexpr size_t kWsIndices = 512;     // up to 256 u32 row indices
+constexpr size_t kWsRecoverRect = 1536;
 constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
 constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
@@ -92,7 +97,7 @@ class PinnedWords {
         if (!pool().empty()) {
             p_ = pool().back();
             pool().pop_back();
-        } else if (hipHostMalloc((void **)&p_, 64, hipHostMallocDefault) != hipSuccess) {
+        } else if (hipHostMalloc((void **)&p_, 256, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             p_ = nullptr;
         }
@@ -560,10 +565,10 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ~WsGuard() { if (own) (void)hipFree(p); }
     } guard{ws, own_ws};
 
-    auto *d_key = (unsigned long long *)(ws + kWsTask);
-    auto *d_stats = d_key + 1;
-    auto *d_ncomb = d_key + 2;
-    auto *d_ctr = d_key + 3;
+    auto *d_key = (unsigned long long *)(ws + kWsKey);
+    auto *d_stats = (unsigned long long *)(ws + kWsCounts);
+    auto *d_ncomb = d_stats + 1;
+    auto *d_ctr = (unsigned long long *)(ws + kWsCtr);
     auto *d_rects = (bz::Rect *)(ws + kWsRects);
 
     hipEvent_t ev0, ev1;
@@ -593,7 +598,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, size_t> on_device;
     size_t rects_used = 0;
     PinnedWords pinned;
-    unsigned long long stack_words[3];
+    unsigned long long stack_words[kWsReadBack / 8];
     unsigned long long *words = pinned.get(stack_words);
     std::map<std::pair<uint32_t, uint32_t>, bz::SchedPlan> splans;            // (g, slots) -> prefix tasks
     struct DevBuf {
@@ -697,20 +702,20 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
                 BZ_HIP(hipEventRecord(ev1, st));
             }
-            BZ_HIP(hipMemcpyAsync(words, d_key, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            BZ_HIP(hipMemcpyAsync(words, ws, kWsReadBack, hipMemcpyDeviceToHost, st));
             BZ_HIP(hipStreamSynchronize(st));
             float ms = 0.f;
             BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
             res->kernel_s += ms * 1e-3;
             res->launches++;
             const uint32_t tmin = words[0] == ~0ull ? 0xffffffffu : (uint32_t)(words[0] >> bz::kTileBits);
-            const uint64_t ncomb = words[2];
+            const uint64_t ncomb = words[kWsCounts / 8 + 1];
             const bool complete = ncomb == bz::binom_sat(k, g);
             res->combinations += ncomb;
             if (res->stats && res->stats_len < res->stats_cap) {
                 bz_level_stat &s = res->stats[res->stats_len];
                 s.matrix = (uint16_t)j; s.level = (uint16_t)g; s.min_weight = tmin;
-                s.count_at_min = stats ? (words[1] & ((1ull << 55) - 1)) : 0;
+                s.count_at_min = stats ? (words[kWsCounts / 8] & ((1ull << 55) - 1)) : 0;
                 s.combinations = ncomb;
             }
             res->stats_len++;
