@@ -37,11 +37,24 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes per launch of the enumeration kernel on the [192,64] workload from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads for
 # a plain copy of known size: x2 and x1), valid for the kernel sources whose
-# hash is given and the tiling the counters were taken with (slots per lane,
-# tiles per resident wave); any other build or tiling reports traffic as
-# unmeasured.
-ENUM_TRAFFIC = {"sources_sha256_16": "0df5936f60837891", "workload": "plain192", "slots_per_lane": 16,
-                "tiles_per_wave": 4, "bytes_per_launch": (732.07 * 2 + 114.97) * 1024}
+# hash is given and the tilings the counters were taken with, keyed by (slots
+# per lane, tiles per resident wave); any other build or tiling reports traffic
+# as unmeasured. Values: (FETCH_SIZE mean, WRITE_SIZE mean) in KiB per launch.
+ENUM_TRAFFIC = {"sources_sha256_16": "21511e0b9bb6f459", "workload": "plain192",
+                "kib_per_launch": {(16, 4): (162.88, 114.97), (16, 8): (162.93, 114.97),
+                                   (8, 4): (124.83, 128.24), (8, 8): (124.93, 128.23),
+                                   (8, 16): (124.97, 128.23)}}
+
+
+def enum_traffic_bytes(workload: str, tuned) -> float | None:
+    """Scaled HBM bytes per enumeration launch for this build, workload and tiling, else None."""
+    if kernel_sources_hash() != ENUM_TRAFFIC["sources_sha256_16"] or workload != ENUM_TRAFFIC["workload"]:
+        return None
+    key = ((tuned or {}).get("slots_per_lane"), (tuned or {}).get("tiles_per_wave"))
+    if key not in ENUM_TRAFFIC["kib_per_launch"]:
+        return None
+    fetch, write = ENUM_TRAFFIC["kib_per_launch"][key]
+    return (fetch * 2 + write) * 1024
 KERNEL_SOURCES = ("bz_kernels.hip", "bz_tile.h", "bz_kernels.h", "bz_internal.h", "bz_plan.cpp")
 
 
@@ -307,12 +320,7 @@ def main():
             "peak": PEAK_INT32_TOPS,
             "unit": "TOP/s (int32 lane operations)",
             "frac": achieved / PEAK_INT32_TOPS,
-            "traffic": (ENUM_TRAFFIC["bytes_per_launch"]
-                        if (kernel_sources_hash() == ENUM_TRAFFIC["sources_sha256_16"]
-                            and args.workload == ENUM_TRAFFIC["workload"]
-                            and (tuned or {}).get("slots_per_lane") == ENUM_TRAFFIC["slots_per_lane"]
-                            and (tuned or {}).get("tiles_per_wave") == ENUM_TRAFFIC["tiles_per_wave"])
-                        else None),
+            "traffic": enum_traffic_bytes(args.workload, tuned),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": 0,
             "kernel": "bz_enum_kernel",
