@@ -60,20 +60,21 @@ using bz::fail;
 using bz::g_err;
 using bz::now_s;
 
-// Workspace layout of one search (bytes). The words many waves touch each get
-// a 128-byte line: the key every tile polls, the statistics and combination
-// count (added once per wave), the schedules' claim counter.
-constexpr size_t kWsKey = 0;           // (min weight << 55) | tile
-constexpr size_t kWsCounts = 128;      // statistics word, then the combination count
-constexpr size_t kWsCtr = 256;         // claim counter of the queue schedules
-constexpr size_t kWsReadBack = 144;    // bytes [0, 144): the key, then (at 128) the two counts
+// Workspace layout of one search (bytes). A window of up to kChainMax tasks
+// runs between two host synchronisations; each task has a record of
+// kRecWords words (key, counts and claim counter on separate 128-byte lines),
+// after the window's bounds (bz::ChainState).
 constexpr size_t kWsRecover = 384;     // flag, len (u32), codeword (4 x u64)
 constexpr size_t kWsIndices = 512;     // up to 256 u32 row indices
-constexpr size_t kWsRecoverRect = 1536;
 constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
 constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
-constexpr size_t kWsBytes = kWsRects + kMaxRects * sizeof(bz::Rect);
+constexpr uint32_t kChainMax = 32;
+constexpr size_t kRecBytes = bz::kRecWords * 8;
+constexpr size_t kWsChain = kWsRects + kMaxRects * sizeof(bz::Rect);   // ChainState, then the records
+constexpr size_t kChainBytes = 128 + kChainMax * kRecBytes;
+constexpr size_t kWsBytes = kWsChain + kChainBytes;
+static_assert(sizeof(bz::ChainState) <= 128, "bounds fit their line");
 
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
@@ -87,9 +88,13 @@ uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t 
     return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)std::max<int64_t>(0, extra);
 }
 
-// Pinned host words for the per-task read-back of a search (a copy into
-// pageable memory goes through a staging buffer). Buffers are taken from and
-// returned to a process-wide pool and kept until the process ends.
+// Pinned host memory for the read-back of a window and for staging the
+// tilings and prefix rows a window uploads (a copy from or into pageable memory
+// goes through a staging buffer of the runtime and waits for the stream).
+// Buffers are taken from and returned to a process-wide pool and kept until
+// the process ends.
+constexpr size_t kStageBytes = 64 * 1024;
+constexpr size_t kPinnedBytes = kChainBytes + kStageBytes;
 class PinnedWords {
   public:
     PinnedWords() {
@@ -97,22 +102,24 @@ class PinnedWords {
         if (!pool().empty()) {
             p_ = pool().back();
             pool().pop_back();
-        } else if (hipHostMalloc((void **)&p_, 256, hipHostMallocDefault) != hipSuccess) {
+        } else if (hipHostMalloc((void **)&p_, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             p_ = nullptr;
         }
+        if (!p_) fallback_.resize(kPinnedBytes / 8);
     }
     ~PinnedWords() {
         if (!p_) return;
         std::lock_guard<std::mutex> lk(mu());
         pool().push_back(p_);
     }
-    unsigned long long *get(unsigned long long *fallback) { return p_ ? p_ : fallback; }
+    unsigned long long *get() { return p_ ? p_ : fallback_.data(); }
 
   private:
     static std::mutex &mu() { static std::mutex m; return m; }
     static std::vector<unsigned long long *> &pool() { static std::vector<unsigned long long *> v; return v; }
     unsigned long long *p_ = nullptr;
+    std::vector<unsigned long long> fallback_;
 };
 
 struct Best {
@@ -565,19 +572,24 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ~WsGuard() { if (own) (void)hipFree(p); }
     } guard{ws, own_ws};
 
-    auto *d_key = (unsigned long long *)(ws + kWsKey);
-    auto *d_stats = (unsigned long long *)(ws + kWsCounts);
-    auto *d_ncomb = d_stats + 1;
-    auto *d_ctr = (unsigned long long *)(ws + kWsCtr);
+    auto *d_state = (bz::ChainState *)(ws + kWsChain);
+    auto *d_records = (unsigned long long *)(ws + kWsChain + 128);
     auto *d_rects = (bz::Rect *)(ws + kWsRects);
 
-    hipEvent_t ev0, ev1;
-    BZ_HIP(hipEventCreate(&ev0));
-    BZ_HIP(hipEventCreate(&ev1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } evg{ev0, ev1};
+    // Timing events, created once per thread and device (a search on one
+    // thread runs at a time) and kept until the process ends.
+    thread_local std::map<int, std::pair<hipEvent_t, hipEvent_t>> t_events;
+    auto evit = t_events.find(c->device);
+    if (evit == t_events.end()) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        BZ_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(BZ_EDEVICE, "hipEventCreate");
+        }
+        evit = t_events.emplace(c->device, std::make_pair(e0, e1)).first;
+    }
+    const hipEvent_t ev0 = evit->second.first, ev1 = evit->second.second;
 
     uint32_t U = n - k + 1, L = 1, Lcert = 1;
     Best best;
@@ -591,15 +603,16 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         return BZ_OK;
     }
 
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bz::LevelPlan> plans;   // (g, slots, tiles/wave) -> plan
+    using PlanKey = std::tuple<uint32_t, uint32_t, uint32_t>;                  // (g, slots, tiles/wave)
+    std::map<PlanKey, bz::LevelPlan> plans;
     // Tilings already on the device (rect offset in the workspace): a level's
     // tiling is uploaded once for all its Gamma_j. When the region is full it
-    // starts over; every earlier launch has finished by then.
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, size_t> on_device;
+    // starts over at a window's start; every earlier launch has finished by then.
+    std::map<PlanKey, size_t> on_device;
     size_t rects_used = 0;
     PinnedWords pinned;
-    unsigned long long stack_words[kWsReadBack / 8];
-    unsigned long long *words = pinned.get(stack_words);
+    unsigned long long *words = pinned.get();               // read-back of a window
+    char *stage = (char *)words + kChainBytes;             // uploads of a window
     std::map<std::pair<uint32_t, uint32_t>, bz::SchedPlan> splans;            // (g, slots) -> prefix tasks
     struct DevBuf {
         char *p = nullptr;
@@ -607,42 +620,145 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ~DevBuf() { if (p) (void)hipFree(p); }
     } sbuf;                                                                    // schedule tilings
     const uint64_t resident_waves = (uint64_t)dc.cus * 32;
-    bool done = false;
-    for (uint32_t g = 1; g <= k && L < U && !done; ++g) {
-        if (opt.max_level && g > opt.max_level) { status = BZ_ELIMIT; g_err = "max_level reached"; break; }
-        res->last_level = g;
-        for (uint32_t j = 0; j < c->nsets && !done; ++j) {
-            if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
-            const uint32_t W = c->W(j);
-            uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(W);
-            uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
-            if (!opt.slots_per_lane && !opt.heads_per_tile) {
-                (void)bz::tuned_choice(W, slots, per_wave);
-                if ((double)bz::binom_sat(k, g) < bz::kLargeLevelComb) per_wave = 1;
+    const uint32_t last_j = c->nsets - 1;
+    // Alg. 1's L once every matrix is done at level g
+    auto level_bound = [&](uint32_t g) { return certified(last_j, g, m_f, k_m, k); };
+
+    struct Task {
+        uint32_t j, g, W, slots;
+        const bz::LevelPlan *plan;       // equal-cost tiles, or
+        const bz::SchedPlan *sp;         // the paper's prefix tasks
+        PlanKey key;
+    };
+    auto make_task = [&](uint32_t j, uint32_t g, Task &t) -> bz_status {
+        t = Task{};
+        t.j = j; t.g = g; t.W = c->W(j);
+        uint32_t slots = opt.slots_per_lane ? opt.slots_per_lane : bz::slots_for_w(t.W);
+        uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
+        if (!opt.slots_per_lane && !opt.heads_per_tile) {
+            (void)bz::tuned_choice(t.W, slots, per_wave);
+            if ((double)bz::binom_sat(k, g) < bz::kLargeLevelComb) per_wave = 1;
+        }
+        if (slots == 16 && t.W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
+        if (use_sched) {
+            slots = bz::slots_for_w(t.W);               // the schedule kernel's fixed lane sums
+            auto skey = std::make_pair(g, slots);
+            if (!splans.count(skey)) {
+                std::string err;
+                bz::SchedPlan p;
+                if (!bz::build_sched_plan(k, g, sched_dynamic, opt.prefix, slots, p, err)) return fail(BZ_ELIMIT, err);
+                splans[skey] = std::move(p);
             }
-            if (slots == 16 && W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
-            if (use_sched) slots = bz::slots_for_w(W);      // the schedule kernel's fixed lane sums
-            const bz::LevelPlan *plan = nullptr;
-            const bz::SchedPlan *sp = nullptr;
-            BZ_HIP(bz::launch_task_init(d_key, d_stats, d_ncomb, d_ctr, st));
+            t.sp = &splans[skey];
+        } else {
+            t.key = std::make_tuple(g, slots, per_wave);
+            if (!plans.count(t.key)) {
+                std::string err;
+                bz::LevelPlan p;
+                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
+                    return fail(BZ_ELIMIT, err);
+                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
+                plans[t.key] = std::move(p);
+            }
+            t.plan = &plans[t.key];
+        }
+        t.slots = slots;
+        return BZ_OK;
+    };
+
+    // Tasks run in windows: the host enqueues several (Gamma_j, g) tasks with a
+    // one-thread bookkeeping step after each (bz::ChainState), synchronises
+    // once, then replays Alg. 1's bookkeeping on the read-back records. A
+    // window ends at the task after which the bounds known when it starts
+    // would already stop the search; tasks enqueued past the point where the
+    // device stops (U fell within the window) leave at once. Windows start at
+    // 2 tasks and double up to kChainMax; schedule tasks run one per window.
+    uint32_t next_g = 1, next_j = 0;         // the next task in Alg. 1's order
+    uint32_t window = 2;
+    bool done = false;
+    std::vector<Task> win;
+    std::vector<bz::Rect> staged;
+    while (!done) {
+        if (next_j == 0) {
+            if (next_g > k || L >= U) break;
+            if (opt.max_level && next_g > opt.max_level) { status = BZ_ELIMIT; g_err = "max_level reached"; break; }
+        }
+        if (opt.cancel && *opt.cancel) { status = BZ_ECANCELED; g_err = "canceled"; break; }
+        win.clear();
+        staged.clear();
+        std::vector<std::pair<PlanKey, size_t>> placed;                         // tilings staged for this window
+        {
+            uint32_t g = next_g, j = next_j, Lw = L, Lc = Lcert;
+            const uint32_t cap = use_sched ? 1u : window;
+            while (win.size() < cap && g <= k && !(opt.max_level && g > opt.max_level)) {
+                Task t;
+                const bz_status e = make_task(j, g, t);
+                if (e != BZ_OK) return e;
+                if (t.plan && !on_device.count(t.key)) {
+                    bool staged_now = false;
+                    for (auto &pl : placed) staged_now = staged_now || pl.first == t.key;
+                    if (!staged_now) {
+                        if (rects_used + t.plan->rects.size() > kMaxRects) {
+                            if (!win.empty()) break;                             // next window
+                            on_device.clear();
+                            rects_used = 0;
+                        }
+                        placed.emplace_back(t.key, rects_used);
+                        staged.insert(staged.end(), t.plan->rects.begin(), t.plan->rects.end());
+                        rects_used += t.plan->rects.size();
+                    }
+                }
+                win.push_back(t);
+                Lc = std::max(Lc, certified(j, g, m_f, k_m, k));
+                bool stop = false;
+                if (!level_stop) {
+                    Lw = std::max(Lw, Lc);
+                    stop = Lw >= U;
+                }
+                if (j == last_j) {
+                    Lw = std::max(Lw, level_bound(g));
+                    stop = stop || Lw >= U;
+                    j = 0;
+                    ++g;
+                } else {
+                    ++j;
+                }
+                if (stop) break;
+            }
+            window = std::min(window * 2, kChainMax);
+        }
+        if (win.empty()) return fail(BZ_EDEVICE, "internal: empty window");
+        if (!staged.empty()) {
+            const size_t off = placed.front().second, bytes = staged.size() * sizeof(bz::Rect);
+            const void *src = staged.data();
+            if (bytes <= kStageBytes) {                 // the previous window's copies have finished
+                std::memcpy(stage, staged.data(), bytes);
+                src = stage;
+            }
+            BZ_HIP(hipMemcpyAsync(d_rects + off, src, bytes, hipMemcpyHostToDevice, st));
+            for (auto &pl : placed) on_device[pl.first] = pl.second;
+        }
+        bz::ChainState init{};
+        init.U = U;
+        init.exit_at = stats ? 0u : Lcert;
+        init.L = L;
+        init.Lcert = Lcert;
+        BZ_HIP(bz::launch_chain_init(d_records, (uint32_t)win.size(), d_state, init,
+                                     want_witness ? (unsigned int *)(ws + kWsRecover) : nullptr, st));
+        for (size_t i = 0; i < win.size(); ++i) {
+            const Task &t = win[i];
+            unsigned long long *rec = d_records + i * bz::kRecWords;
             bz::TaskArgs a{};
-            a.rows = (const uint32_t *)c->dev + c->packed_off[j];
+            a.rows = (const uint32_t *)c->dev + c->packed_off[t.j];
             a.binom = dc.binom;
-            a.key = d_key; a.stats = d_stats; a.ncomb = d_ncomb; a.tile_ctr = d_ctr;
+            a.key = rec + bz::kRecKey; a.stats = rec + bz::kRecStats; a.ncomb = rec + bz::kRecNcomb;
+            a.tile_ctr = rec + bz::kRecCtr;
             a.cancel = (const uint32_t *)opt.cancel;
-            a.k = k; a.k_low = c->k_low(j); a.g = g;
+            a.k = k; a.k_low = c->k_low(t.j); a.g = t.g;
             a.u_prev = U;
             a.exit_at = stats ? 0u : Lcert;
-            if (use_sched) {
-                auto skey = std::make_pair(g, slots);
-                if (!splans.count(skey)) {
-                    std::string err;
-                    bz::SchedPlan p;
-                    if (!bz::build_sched_plan(k, g, sched_dynamic, opt.prefix, slots, p, err))
-                        return fail(BZ_ELIMIT, err);
-                    splans[skey] = std::move(p);
-                }
-                sp = &splans[skey];
+            if (t.sp) {
+                const bz::SchedPlan *sp = t.sp;
                 const size_t eb = align256(sp->entries.size() * sizeof(bz::PlanEntry));
                 const size_t need = eb + sp->rects.size() * sizeof(bz::Rect);
                 if (need > sbuf.cap) {
@@ -665,81 +781,82 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 sa.pre = sp->pre;
                 sa.dist = sched_dist;
                 sa.order = sched_order;
-                const size_t lds = bz::enum_lds_bytes(k, g, W);
-                const uint32_t grid = (uint32_t)dc.cus * (uint32_t)bz::sched_blocks_per_cu(W, j >= m_f, stats, lds);
-                BZ_HIP(hipEventRecord(ev0, st));
-                BZ_HIP(bz::launch_sched(sa, W, j >= m_f, stats, grid, st));
-                BZ_HIP(hipEventRecord(ev1, st));
+                const size_t lds = bz::enum_lds_bytes(k, t.g, t.W);
+                const uint32_t grid =
+                    (uint32_t)dc.cus * (uint32_t)bz::sched_blocks_per_cu(t.W, t.j >= m_f, stats, lds);
+                if (i == 0) BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_sched(sa, t.W, t.j >= m_f, stats, grid, st));
             } else {
-                auto key = std::make_tuple(g, slots, per_wave);
-                if (!plans.count(key)) {
-                    std::string err;
-                    bz::LevelPlan p;
-                    if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
-                        return fail(BZ_ELIMIT, err);
-                    if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
-                    plans[key] = std::move(p);
-                }
-                plan = &plans[key];
-                auto od = on_device.find(key);
-                if (od == on_device.end()) {
-                    if (rects_used + plan->rects.size() > kMaxRects) {
-                        on_device.clear();
-                        rects_used = 0;
-                    }
-                    BZ_HIP(hipMemcpyAsync(d_rects + rects_used, plan->rects.data(),
-                                          plan->rects.size() * sizeof(bz::Rect), hipMemcpyHostToDevice, st));
-                    od = on_device.emplace(key, rects_used).first;
-                    rects_used += plan->rects.size();
-                }
-                a.rects = d_rects + od->second;
-                a.nrects = (uint32_t)plan->rects.size();
-                a.heads_per_tile = plan->heads_per_tile;
-                a.total_tiles = plan->total_tiles;
-                const uint64_t blocks = (plan->total_tiles + 3) / 4;
-                const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
-                BZ_HIP(hipEventRecord(ev0, st));
-                BZ_HIP(bz::launch_enum(a, W, slots, j >= m_f, stats, grid, st));
-                BZ_HIP(hipEventRecord(ev1, st));
+                a.chain = d_state;
+                a.rects = d_rects + on_device.at(t.key);
+                a.nrects = (uint32_t)t.plan->rects.size();
+                a.heads_per_tile = t.plan->heads_per_tile;
+                a.total_tiles = t.plan->total_tiles;
+                const uint64_t blocks = (t.plan->total_tiles + 3) / 4;
+                const uint32_t grid =
+                    (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
+                if (i == 0) BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
+                bz::ChainStep cs{};
+                cs.state = d_state;
+                cs.key = a.key;
+                cs.ncomb = a.ncomb;
+                cs.total = bz::binom_sat(k, t.g);
+                cs.cert_task = certified(t.j, t.g, m_f, k_m, k);
+                cs.last_of_level = t.j == last_j;
+                cs.cert_level = level_bound(t.g);
+                cs.level_stop = level_stop;
+                cs.stats = stats;
+                BZ_HIP(bz::launch_chain_step(cs, st));
             }
-            BZ_HIP(hipMemcpyAsync(words, ws, kWsReadBack, hipMemcpyDeviceToHost, st));
-            BZ_HIP(hipStreamSynchronize(st));
-            float ms = 0.f;
-            BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-            res->kernel_s += ms * 1e-3;
+        }
+        BZ_HIP(hipEventRecord(ev1, st));
+        BZ_HIP(hipMemcpyAsync(words, ws + kWsChain, 128 + win.size() * kRecBytes, hipMemcpyDeviceToHost, st));
+        BZ_HIP(hipStreamSynchronize(st));
+        float ms = 0.f;
+        BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        res->kernel_s += ms * 1e-3;
+
+        bool stopped = false;                  // L reached U at a level start inside the window
+        for (size_t i = 0; i < win.size() && !done; ++i) {
+            const Task &t = win[i];
+            if (i > 0 && t.j == 0 && L >= U) { stopped = true; break; }
+            const unsigned long long *r = words + 16 + i * bz::kRecWords;
+            const uint32_t j = t.j, g = t.g, slots = t.slots;
+            res->last_level = g;
             res->launches++;
-            const uint32_t tmin = words[0] == ~0ull ? 0xffffffffu : (uint32_t)(words[0] >> bz::kTileBits);
-            const uint64_t ncomb = words[kWsCounts / 8 + 1];
+            const uint32_t tmin = r[bz::kRecKey] == ~0ull ? 0xffffffffu : (uint32_t)(r[bz::kRecKey] >> bz::kTileBits);
+            const uint64_t ncomb = r[bz::kRecNcomb];
             const bool complete = ncomb == bz::binom_sat(k, g);
             res->combinations += ncomb;
             if (res->stats && res->stats_len < res->stats_cap) {
                 bz_level_stat &s = res->stats[res->stats_len];
                 s.matrix = (uint16_t)j; s.level = (uint16_t)g; s.min_weight = tmin;
-                s.count_at_min = stats ? (words[kWsCounts / 8] & ((1ull << 55) - 1)) : 0;
+                s.count_at_min = stats ? (r[bz::kRecStats] & ((1ull << 55) - 1)) : 0;
                 s.combinations = ncomb;
             }
             res->stats_len++;
             if (tmin < U || (tmin == U && !best.have)) {
                 U = tmin;
-                best.have = true; best.j = j; best.g = g; best.tile = words[0] & bz::kTileMask;
+                best.have = true; best.j = j; best.g = g; best.tile = r[bz::kRecKey] & bz::kTileMask;
                 best.slots = slots;
                 const bz::Rect *rr = nullptr;
                 size_t nr = 0;
-                if (sp) {
+                if (t.sp) {
                     // key tile = prefix task * stride + tile of that task's completion plan
-                    const uint64_t task = best.tile / sp->stride;
-                    best.tile -= task * sp->stride;
+                    const uint64_t task = best.tile / t.sp->stride;
+                    best.tile -= task * t.sp->stride;
                     uint32_t lo = 0;
-                    bz::sched_prefix(*sp, k, g, sched_order, task, best.pre, lo);
-                    const bz::PlanEntry &e = sp->entries[lo];
-                    rr = sp->rects.data() + e.rect_off;
+                    bz::sched_prefix(*t.sp, k, g, sched_order, task, best.pre, lo);
+                    const bz::PlanEntry &e = t.sp->entries[lo];
+                    rr = t.sp->rects.data() + e.rect_off;
                     nr = e.nrects;
                     best.ht = e.heads_per_tile;
                 } else {
                     best.pre.clear();
-                    rr = plan->rects.data();
-                    nr = plan->rects.size();
-                    best.ht = plan->heads_per_tile;
+                    rr = t.plan->rects.data();
+                    nr = t.plan->rects.size();
+                    best.ht = t.plan->heads_per_tile;
                 }
                 size_t lo = 0, hi = nr - 1;
                 while (lo < hi) {
@@ -748,6 +865,8 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 }
                 best.rect = rr[lo];
             }
+            next_j = j == last_j ? 0 : j + 1;
+            next_g = j == last_j ? g + 1 : g;
             if (opt.cancel && *opt.cancel && !complete) { status = BZ_ECANCELED; g_err = "canceled"; done = true; break; }
             if (!complete) {
                 // a wave only leaves a task early once U <= the certified bound
@@ -761,9 +880,14 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 L = std::max(L, Lcert);
                 if (L >= U) done = true;
             }
+            if (!done && j == last_j) L = std::max(L, level_bound(g));
         }
-        // Alg. 1's L once every matrix is done at level g
-        if (!done && status == BZ_OK) L = std::max(L, certified(k_m ? m_f : m_f - 1, g, m_f, k_m, k));
+        if (!use_sched) {
+            // the device took the same decisions: it stopped exactly where the host does
+            const bool host_stop = done || stopped || (next_j == 0 && L >= U);
+            const bool dev_stop = ((const bz::ChainState *)words)->done != 0;
+            if (host_stop != dev_stop) return fail(BZ_EDEVICE, "internal: device and host bookkeeping disagree");
+        }
     }
     res->lower_bound = L;
     res->upper_bound = U;
@@ -778,8 +902,8 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ra.rows = (const uint32_t *)c->dev + c->packed_off[j];
         ra.full_rows = (const uint64_t *)((char *)c->dev + c->dev_full_off) + (size_t)j * k * bz::kHostWords;
         ra.binom = dc.binom;
-        ra.rect = (const bz::Rect *)(ws + kWsRecoverRect);
-        ra.flag = (unsigned int *)(ws + kWsRecover);
+        ra.rect = best.rect;
+        ra.flag = (unsigned int *)(ws + kWsRecover);        // cleared by the last window's init
         ra.indices_len = (uint32_t *)(ws + kWsRecover + 4);
         ra.codeword = (unsigned long long *)(ws + kWsRecover + 8);
         ra.indices = (uint32_t *)(ws + kWsIndices);
@@ -787,14 +911,14 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         ra.W = c->W(j); ra.k_low = c->k_low(j); ra.target = U;
         ra.pre_n = (uint32_t)best.pre.size();
         ra.pre_rows = (const uint32_t *)(ws + kWsPreRows);
-        if (ra.pre_n)
-            BZ_HIP(hipMemcpyAsync(ws + kWsPreRows, best.pre.data(), ra.pre_n * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                  st));
-        BZ_HIP(hipMemcpyAsync(ws + kWsRecoverRect, &best.rect, sizeof(bz::Rect), hipMemcpyHostToDevice, st));
-        BZ_HIP(hipMemsetAsync(ws + kWsRecover, 0, 64, st));
+        if (ra.pre_n) {
+            if (ra.pre_n > 64) return fail(BZ_EDEVICE, "internal: prefix longer than its buffer");
+            std::memcpy(stage, best.pre.data(), ra.pre_n * sizeof(uint32_t));
+            BZ_HIP(hipMemcpyAsync(ws + kWsPreRows, stage, ra.pre_n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        }
         BZ_HIP(bz::launch_recover(ra, st));
-        unsigned long long back[5];
-        BZ_HIP(hipMemcpyAsync(back, ws + kWsRecover, sizeof(back), hipMemcpyDeviceToHost, st));
+        unsigned long long *back = words;
+        BZ_HIP(hipMemcpyAsync(back, ws + kWsRecover, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         BZ_HIP(hipStreamSynchronize(st));
         if ((uint32_t)back[0] != 1u) return fail(BZ_EDEVICE, "internal: witness not found in its tile");
         for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = back[1 + w];

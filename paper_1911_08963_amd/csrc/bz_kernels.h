@@ -7,6 +7,38 @@
 
 namespace bz {
 
+// Bounds of a single search held on the device while a window of its tasks
+// runs without the host: the enumeration kernel takes U and its exit bound
+// from here, and a one-thread step after each task applies Alg. 1's
+// bookkeeping to it (lower U, raise the certified bound, stop).
+struct ChainState {
+    uint32_t U;                  // upper bound from completed tasks
+    uint32_t exit_at;            // the next task stops once U <= this (0 = never)
+    uint32_t done;               // nonzero: the search has stopped, later tasks do nothing
+    uint32_t L;                  // Alg. 1's lower bound
+    uint32_t Lcert;              // bound certified by the completed tasks
+    uint32_t _pad[3];
+};
+
+// Per-task words of a window, one record each: the key, the statistics and
+// combination count, the schedules' claim counter, each on a 128-byte line.
+constexpr uint32_t kRecWords = 48;       // 384 bytes
+constexpr uint32_t kRecKey = 0, kRecStats = 16, kRecNcomb = 17, kRecCtr = 32;
+
+// One task's step of the device-side bookkeeping (run after the task).
+struct ChainStep {
+    ChainState *state;
+    const unsigned long long *key;     // the task's key and combination count
+    const unsigned long long *ncomb;
+    uint64_t total;                    // C(k, g): what a complete task enumerates
+    uint32_t cert_task;                // bound certified once this task is complete
+    uint32_t last_of_level;            // the level's last matrix: Alg. 1's L and stop check
+    uint32_t cert_level;               // Alg. 1's L once the level is complete
+    uint32_t level_stop;               // stop only at level ends (Alg. 1 as printed)
+    uint32_t stats;                    // statistics mode: no exit inside a task
+    uint32_t _pad;
+};
+
 // One (Gamma_j, g) task: arguments of the enumeration kernel.
 struct TaskArgs {
     const uint32_t *rows;        // k x W packed rows of Gamma_j (device)
@@ -22,13 +54,14 @@ struct TaskArgs {
     uint64_t total_tiles;
     uint32_t u_prev;             // upper bound from completed tasks
     uint32_t exit_at;            // stop when the upper bound is <= this (0 = never)
+    const ChainState *chain;     // when set: u_prev and exit_at come from here, and a stopped search skips the task
 };
 
 struct RecoverArgs {
     const uint32_t *rows;        // packed rows of Gamma_j
     const uint64_t *full_rows;   // k x kHostWords full rows of Gamma_j
     const uint64_t *binom;
-    const Rect *rect;            // the winning tile's rectangle (device)
+    Rect rect;                   // the winning tile's rectangle
     unsigned int *flag;          // 0 before the launch
     uint32_t *indices;           // up to g row indices
     uint32_t *indices_len;
@@ -200,6 +233,11 @@ hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool parti
 size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W);
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
+// Resets n task records (kRecWords each), writes the window's starting bounds
+// and zeroes *clear (the witness flag) when it is set.
+hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState *state, const ChainState &init,
+                             unsigned int *clear, hipStream_t st);
+hipError_t launch_chain_step(const ChainStep &s, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
 
 // ---- the paper's prefix-task schedules (bz_sched.hip, bz_sched.h)

@@ -21,6 +21,14 @@ namespace bz {
 
 template <int W, int SLOTS, bool PARTIAL, bool STATS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS || PARTIAL) ? 1 : 5))) void bz_enum_kernel(TaskArgs a) {
+    // In a window the bounds come from the previous task's step; once the
+    // search has stopped the task is empty (the whole work-group leaves).
+    uint32_t u_prev = a.u_prev, exit_at = a.exit_at;
+    if (a.chain) {
+        if (a.chain->done) return;
+        u_prev = a.chain->U;
+        exit_at = a.chain->exit_at;
+    }
     extern __shared__ uint64_t smem[];
     const uint32_t bt = a.g + 1;                          // binomial row stride in LDS
     uint64_t *sbin = smem;                                // (k+1) x (g+1)
@@ -57,10 +65,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
     for (uint64_t it = first; it < a.total_tiles; it += stride) {
         const uint64_t tile = uni64(it);
         bool stop = false;
-        if (a.exit_at) {
+        if (exit_at) {
             unsigned long long kv = __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t cur = min((uint32_t)(kv >> kTileBits), a.u_prev);
-            stop = uni(cur) <= a.exit_at;
+            uint32_t cur = min((uint32_t)(kv >> kTileBits), u_prev);
+            stop = uni(cur) <= exit_at;
         }
         if (a.cancel) {
             uint32_t cv = __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -89,6 +97,47 @@ __global__ void bz_task_init_kernel(unsigned long long *key, unsigned long long 
     }
 }
 
+// Resets the records of a window's tasks (key and statistics to "none",
+// counts to 0), writes the bounds the window starts from, and clears the
+// witness flag when given.
+__global__ void bz_chain_init_kernel(unsigned long long *records, uint32_t n, ChainState *state, ChainState init,
+                                     unsigned int *clear) {
+    const uint32_t i = threadIdx.x;
+    if (i < n) {
+        unsigned long long *r = records + (size_t)i * kRecWords;
+        r[kRecKey] = ~0ull;
+        r[kRecStats] = ~0ull;
+        r[kRecNcomb] = 0;
+        r[kRecCtr] = 0;
+    }
+    if (i == 0) *state = init;
+    if (i == 1 && clear) *clear = 0u;
+}
+
+// Alg. 1's bookkeeping after one task of a window, on the device: lower U by
+// the task's minimum, and, when the task is complete, raise the certified
+// bound (and at the level's end Alg. 1's L) and stop once L reaches U. A task
+// that is not complete ended early (certified bound reached, or canceled): the
+// search stops. The host replays the same steps on the read-back records.
+__global__ void bz_chain_step_kernel(ChainStep s) {
+    if (threadIdx.x != 0) return;
+    ChainState c = *s.state;
+    if (c.done) return;
+    const unsigned long long key = *s.key;
+    const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
+    c.U = min(c.U, tmin);
+    if (*s.ncomb != s.total) {
+        c.done = 1;
+    } else {
+        c.Lcert = max(c.Lcert, s.cert_task);
+        c.exit_at = s.stats ? 0u : c.Lcert;
+        if (!s.level_stop) c.L = max(c.L, c.Lcert);
+        if (s.last_of_level) c.L = max(c.L, s.cert_level);
+        if ((!s.level_stop || s.last_of_level) && c.L >= c.U) c.done = 1;
+    }
+    *s.state = c;
+}
+
 // Witness recovery: one thread per combination of the winning tile, each
 // computed from scratch (no shared state with the enumeration kernel), joined
 // to the rows of the tile's prefix task when it has one. The first thread
@@ -97,7 +146,7 @@ __global__ void bz_task_init_kernel(unsigned long long *key, unsigned long long 
 __global__ void bz_recover_kernel(RecoverArgs a) {
     const uint64_t lane_items = (uint64_t)kWaveSize * a.slots;
     const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const Rect R = *a.rect;
+    const Rect R = a.rect;
     const uint64_t local = a.tile - R.tile_begin;
     const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
     const uint64_t li = id % lane_items, hs = id / lane_items;
@@ -202,6 +251,18 @@ size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W) {
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats, unsigned long long *ncomb,
                             unsigned long long *ctr, hipStream_t st) {
     hipLaunchKernelGGL(bz_task_init_kernel, dim3(1), dim3(64), 0, st, key, stats, ncomb, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState *state, const ChainState &init,
+                             unsigned int *clear, hipStream_t st) {
+    if (n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bz_chain_init_kernel, dim3(1), dim3(64), 0, st, records, n, state, init, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_step(const ChainStep &s, hipStream_t st) {
+    hipLaunchKernelGGL(bz_chain_step_kernel, dim3(1), dim3(64), 0, st, s);
     return hipGetLastError();
 }
 
