@@ -637,7 +637,10 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
         uint32_t per_wave = bz::kFixedTilesPerWave;     // tiles per resident wave
         if (!opt.slots_per_lane && !opt.heads_per_tile) {
             (void)bz::tuned_choice(t.W, slots, per_wave);
-            if ((double)bz::binom_sat(k, g) < bz::kLargeLevelComb) per_wave = 1;
+            const double comb = (double)bz::binom_sat(k, g);
+            if (comb < bz::kLargeLevelComb) per_wave = 1;
+            if (comb < bz::kTinyLevelComb) slots = 2;
+            else if (comb < bz::kSmallLevelComb) slots = std::min(slots, 8u);
         }
         if (slots == 16 && t.W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
         if (use_sched) {

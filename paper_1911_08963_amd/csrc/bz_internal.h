@@ -36,6 +36,13 @@ constexpr uint32_t kFixedTilesPerWave = 4;
 // per resident wave: there a tile's setup weighs more than the balance that
 // smaller tiles buy.
 constexpr double kLargeLevelComb = 2e10;
+// Lane sums per lane on the smallest levels of a single-code search: there a
+// wave runs one short tile whose time is mostly the setup that unranks its
+// lane subsets (a chain of binomial look-ups per slot), so fewer slots finish
+// sooner. Measured per level on k = 64, W = 2: level 2 (2016 sums) 6.5 us with
+// 2 slots against 19 us with 16; level 5 (7.6e6 sums) 22 us with 8 against 37.
+constexpr double kTinyLevelComb = 2097152.0;      // 2^21: 2 slots
+constexpr double kSmallLevelComb = 16777216.0;    // 2^24: at most 8 slots
 
 // One product of two colex subset spaces inside the g-subsets of [0, k):
 // every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a
