@@ -105,6 +105,36 @@ __device__ __forceinline__ uint32_t colex_digit(const uint64_t *sb, uint32_t bt,
     return lo;
 }
 
+// The same digit and its binomial C(c, i), with few dependent look-ups: the
+// start is the root of C(c, i) ~ (c - (i - 1)/2)^i / i! (lf = log2(i!)), and
+// steps up or down correct it, so the result is exact whatever the estimate
+// (C(i - 1, i) = 0 <= r ends the way down, c <= hi the way up). Two
+// independent look-ups usually settle a digit, where a bisection costs one
+// dependent look-up per halving of [i - 1, hi].
+__device__ __forceinline__ uint32_t colex_digit_est(const uint64_t *sb, uint32_t bt, uint32_t i, uint32_t hi,
+                                                    uint64_t r, float lf, uint64_t &bc) {
+    const float fi = (float)i;
+    const float root =
+        __builtin_amdgcn_exp2f((__builtin_amdgcn_logf((float)r) + lf) * __builtin_amdgcn_rcpf(fi));
+    uint32_t c = (uint32_t)fminf(fmaxf(root + 0.5f * (fi - 1.0f), fi - 1.0f), (float)hi);
+    uint64_t b0 = sb[c * bt + i];
+    uint64_t b1 = c < hi ? sb[(c + 1) * bt + i] : ~0ull;
+    if (b0 > r) {
+        do {
+            --c;
+            b0 = sb[c * bt + i];
+        } while (b0 > r);
+    } else {
+        while (b1 <= r) {
+            ++c;
+            b0 = b1;
+            b1 = c < hi ? sb[(c + 1) * bt + i] : ~0ull;
+        }
+    }
+    bc = b0;
+    return c;
+}
+
 // The same for uniform values, with binomials through the scalar cache.
 __device__ __forceinline__ uint32_t colex_digit_s(cptr64 gb, uint32_t i, uint32_t lo, uint32_t hi,
                                                    uint64_t r) {
@@ -161,6 +191,8 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
     const uint64_t base = t.lb * (kWaveSize * SLOTS);
     const uint32_t nvalid =
         uni(t.lane_count > base ? (uint32_t)umin64(t.lane_count - base, (uint64_t)kWaveSize * SLOTS) : 0u);
+    float lf_top = 0.f;                            // log2(lane_t!)
+    for (uint32_t j = 2; j <= t.lane_t; ++j) lf_top += __builtin_amdgcn_logf((float)j);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const uint64_t first = base + (uint64_t)s * kWaveSize;
@@ -173,13 +205,16 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
         if (first >= t.lane_count) continue;      // uniform: a slot with no valid lane
         uint64_t r = valid ? q : 0ull;
         uint32_t hi = t.lane_n - 1;
+        float lf = lf_top;
         for (uint32_t i = t.lane_t; i >= 1; --i) {
-            uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
-            r -= sbin[c * bt + i];
+            uint64_t bc;
+            const uint32_t c = colex_digit_est(sbin, bt, i, hi, r, lf, bc);
+            r -= bc;
             const uint32_t row = t.lane_off + c;
 #pragma unroll
             for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
             low[s] += (row < k_low) ? 1u : 0u;
+            lf -= __builtin_amdgcn_logf((float)i);
             hi = c - 1;
         }
     }
