@@ -43,10 +43,10 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # as unmeasured. Values: (FETCH_SIZE mean, WRITE_SIZE mean) in KiB per launch
 # of the dominant kernel (the 17 launches of a search on levels of at least
 # 2^24 sums).
-ENUM_TRAFFIC = {"sources_sha256_16": "451e4fce43bae9a8", "workload": "plain192",
-                "kib_per_launch": {(16, 4): (212.95, 214.36), (16, 8): (213.08, 214.34),
-                                   (8, 4): (164.56, 237.65), (8, 8): (164.99, 237.67),
-                                   (8, 16): (164.76, 237.65)}}
+ENUM_TRAFFIC = {"sources_sha256_16": "a88685d7407bd890", "workload": "plain192",
+                "kib_per_launch": {(16, 4): (196.38, 214.51), (16, 8): (196.17, 214.55),
+                                   (8, 4): (151.04, 237.92), (8, 8): (151.05, 237.90),
+                                   (8, 16): (151.26, 237.92)}}
 
 
 def enum_traffic_bytes(workload: str, tuned) -> float | None:
