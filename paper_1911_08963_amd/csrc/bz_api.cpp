@@ -467,10 +467,19 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
         return BZ_OK;
     }
     if (hipMalloc(&c->dev, c->dev_bytes) != hipSuccess) return fail(BZ_ENOMEM, "device allocation for Gamma_j");
-    hipError_t e1 = hipMemcpy(c->dev, dev_packed.data(), dev_packed.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    hipError_t e2 = hipMemcpy((char *)c->dev + pbytes, c->full_rows.data(),
-                              c->full_rows.size() * sizeof(bz::HostRow), hipMemcpyHostToDevice);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    // one upload of the whole layout, from pinned memory when it fits (a copy
+    // from pageable memory goes through the runtime's staging buffer)
+    PinnedWords pinned;
+    std::vector<char> pageable;
+    char *img = (char *)pinned.get();
+    if (c->dev_bytes > kPinnedBytes) {
+        pageable.resize(c->dev_bytes);
+        img = pageable.data();
+    }
+    std::memset(img, 0, pbytes);
+    std::memcpy(img, dev_packed.data(), dev_packed.size() * sizeof(uint32_t));
+    std::memcpy(img + pbytes, c->full_rows.data(), c->full_rows.size() * sizeof(bz::HostRow));
+    if (hipMemcpy(c->dev, img, c->dev_bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(c->dev);
         return fail(BZ_EDEVICE, "upload of Gamma_j");
     }
