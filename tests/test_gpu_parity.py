@@ -59,6 +59,9 @@ def _compare(bz, G, n, *, level_stop=False, slots=0, heads=0, max_level=0, tag="
     assert got.upper_bound == ref.upper_bound and got.lower_bound == ref.lower_bound
     assert [tuple(s) for s in got.stats] == [tuple(s) for s in ref.stats]
     assert got.combinations == ref.combinations
+    # tasks run in windows; those enqueued past the stop return at once and
+    # are not counted: the search ran exactly the oracle's tasks
+    assert got.launches == len(ref.stats)
     if got.status == 0:
         _check_witness(got, G, n)
     fast = bz.min_distance(code, level_stop=level_stop, slots_per_lane=slots, heads_per_tile=heads,
