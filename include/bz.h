@@ -185,6 +185,30 @@ bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opt
  * recovery kernel re-finds in the winning tile. */
 bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
 
+/* A search that allocates nothing, for callers that cannot allocate device
+ * or pinned memory while they run: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.
+ *
+ * Gives exactly what bz_min_distance gives for the same code and options, but
+ * works in a device array inside the library instead of a workspace:
+ *  - The array holds BZ_NOALLOC_SCRATCH_BYTES per device (the binomial table
+ *    and one search's workspace); each device the library runs on keeps its
+ *    own copy until the process ends. o->workspace must be NULL.
+ *  - The first call on a device looks up the array's address there and copies
+ *    the binomial table into it (a copy, no allocation), and sets aside the
+ *    host memory for the read-backs. Later calls only use them.
+ *  - Calls on one device share its array, so they would race if they
+ *    overlapped: the library serialises them with a lock per device (calls on
+ *    different devices run concurrently). Each call initialises every part of
+ *    the array it reads; nothing carries over from the previous call.
+ *  - Read-backs go through ordinary host memory, and kernel_s stays 0 (no
+ *    timing events).
+ * Limits and errors: as bz_min_distance; EINVAL for a workspace or for
+ * schedules 1..8 (their tilings need device memory of their own); ELIMIT for a
+ * level whose tiling needs more than the 16384 rectangles the array holds. */
+#define BZ_NOALLOC_SCRATCH_BYTES 1572864u
+bz_status bz_min_distance_noalloc(bz_code *code, const bz_opts *o, bz_result *res);
+
 /* Many codes at once: one persistent launch drains a device queue of
  * (code, Gamma_j, g, tile) work for all of them. res[i] and per_code[i] belong
  * to codes[i]. Returns the first per-code error, or BZ_OK. */

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbz.so")
 SOURCES = ["bz_api.cpp", "bz_prepare.cpp", "bz_plan.cpp", "bz_kernels.hip", "bz_batch.hip",
            "bz_server.cpp", "bz_tune.cpp",
-           "bz_count.hip", "bz_count.cpp", "bz_sched.hip", "bz_sched.cpp"]
+           "bz_count.hip", "bz_count.cpp", "bz_sched.hip", "bz_sched.cpp", "bz_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

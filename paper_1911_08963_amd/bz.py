@@ -115,6 +115,7 @@ def _signatures(lib):
         "bz_free": ([vp], None),
         "bz_workspace_bytes": ([P(vp), u32, P(Opts), P(ctypes.c_size_t)], ctypes.c_int),
         "bz_min_distance": ([vp, P(Opts), P(Result)], ctypes.c_int),
+        "bz_min_distance_noalloc": ([vp, P(Opts), P(Result)], ctypes.c_int),
         "bz_min_distance_batch": ([P(vp), u32, P(Opts), P(Result), P(ctypes.c_int)], ctypes.c_int),
         "bz_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "bz_last_error": ([], ctypes.c_char_p),
@@ -278,6 +279,25 @@ def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = stream if stream is not None else torch.cuda.current_stream(dev)
     ws = _workspace(dev, workspace_bytes())
+    return _search(lib().bz_min_distance, code, stats, level_stop, witness, max_level, slots_per_lane,
+                   heads_per_tile, stats_cap, stream, ws, cancel, raise_on_error, schedule, prefix)
+
+
+def min_distance_noalloc(code: Code, *, stats: bool = False, level_stop: bool = False,
+                         witness: bool = True, max_level: int = 0, slots_per_lane: int = 0,
+                         heads_per_tile: int = 0, stats_cap: int = 4096, stream=None,
+                         cancel=None, raise_on_error: bool = True) -> SearchResult:
+    """bz_min_distance_noalloc on the current torch stream: the library's own device scratch
+    array, no workspace and no allocation."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    return _search(lib().bz_min_distance_noalloc, code, stats, level_stop, witness, max_level,
+                   slots_per_lane, heads_per_tile, stats_cap, stream, None, cancel, raise_on_error, 0, 0)
+
+
+def _search(fn, code, stats, level_stop, witness, max_level, slots_per_lane, heads_per_tile, stats_cap,
+            stream, ws, cancel, raise_on_error, schedule, prefix) -> SearchResult:
     flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
         (0 if witness else BZ_F_NO_WITNESS)
     o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
@@ -289,7 +309,7 @@ def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
     r.witness = wit.ctypes.data_as(P(ctypes.c_uint64))
     r.stats = st_buf
     r.stats_cap = stats_cap
-    st = lib().bz_min_distance(code.handle, ctypes.byref(o), ctypes.byref(r))
+    st = fn(code.handle, ctypes.byref(o), ctypes.byref(r))
     if st != BZ_OK and raise_on_error:
         _check(st)
     out = SearchResult(st, r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,

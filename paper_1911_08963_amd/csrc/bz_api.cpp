@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <optional>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -33,16 +34,21 @@ double now_s() {
 static std::mutex g_mu;
 static std::map<int, DeviceConst> g_devconst;
 
+std::vector<uint64_t> binom_table() {
+    std::vector<uint64_t> tab((size_t)kBinomRows * (kBinomT + 1));
+    for (uint32_t x = 0; x < (uint32_t)kBinomRows; ++x)
+        for (uint32_t y = 0; y <= (uint32_t)kBinomT; ++y)
+            tab[(size_t)x * (kBinomT + 1) + y] = binom_sat(x, y);
+    return tab;
+}
+
 bz_status device_const(int dev, DeviceConst &out) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_devconst.find(dev);
     if (it != g_devconst.end()) { out = it->second; return BZ_OK; }
     DeviceConst dc;
     BZ_HIP(hipDeviceGetAttribute(&dc.cus, hipDeviceAttributeMultiprocessorCount, dev));
-    std::vector<uint64_t> tab((size_t)bz::kBinomRows * (bz::kBinomT + 1));
-    for (uint32_t x = 0; x < (uint32_t)bz::kBinomRows; ++x)
-        for (uint32_t y = 0; y <= (uint32_t)bz::kBinomT; ++y)
-            tab[(size_t)x * (bz::kBinomT + 1) + y] = bz::binom_sat(x, y);
+    const std::vector<uint64_t> tab = binom_table();
     BZ_HIP(hipMalloc(&dc.binom, tab.size() * sizeof(uint64_t)));
     BZ_HIP(hipMemcpy(dc.binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     g_devconst[dev] = dc;
@@ -528,7 +534,20 @@ bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opt
     return BZ_OK;
 }
 
-bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
+}  // extern "C"
+
+namespace {
+
+// What a search that allocates nothing works with instead of the library's
+// allocations: the binomial table and the workspace inside the device scratch
+// array, host memory set aside for the read-backs, and no timing events.
+struct NoAllocEnv {
+    DeviceConst dc;
+    char *ws = nullptr;
+    unsigned long long *host = nullptr;   // kPinnedBytes of host memory
+};
+
+bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const NoAllocEnv *na) {
     if (!c || !res) return fail(BZ_EINVAL, "null argument");
     if (!c->dev) return fail(BZ_EINVAL, "code prepared host-only (BZ_PREPARE_HOST_ONLY): submit it to a server");
     bz_opts opt{};
@@ -565,12 +584,18 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     }
     hipStream_t st = (hipStream_t)opt.hip_stream;
     DeviceConst dc;
-    bz_status s0 = device_const(c->device, dc);
-    if (s0 != BZ_OK) return s0;
+    if (na) {
+        dc = na->dc;
+    } else {
+        bz_status s0 = device_const(c->device, dc);
+        if (s0 != BZ_OK) return s0;
+    }
 
-    char *ws = (char *)opt.workspace;
+    char *ws = na ? na->ws : (char *)opt.workspace;
     bool own_ws = false;
-    if (ws) {
+    if (na) {
+        // the scratch array holds the workspace (checked when the library is built)
+    } else if (ws) {
         if (opt.workspace_bytes < kWsBytes) return fail(BZ_ENOMEM, "workspace smaller than bz_workspace_bytes");
     } else {
         if (hipMalloc((void **)&ws, kWsBytes) != hipSuccess) return fail(BZ_ENOMEM, "workspace allocation");
@@ -586,19 +611,24 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     auto *d_rects = (bz::Rect *)(ws + kWsRects);
 
     // Timing events, created once per thread and device (a search on one
-    // thread runs at a time) and kept until the process ends.
-    thread_local std::map<int, std::pair<hipEvent_t, hipEvent_t>> t_events;
-    auto evit = t_events.find(c->device);
-    if (evit == t_events.end()) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        BZ_HIP(hipEventCreate(&e0));
-        if (hipEventCreate(&e1) != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            return fail(BZ_EDEVICE, "hipEventCreate");
+    // thread runs at a time) and kept until the process ends. A search that
+    // allocates nothing is not timed.
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (!na) {
+        thread_local std::map<int, std::pair<hipEvent_t, hipEvent_t>> t_events;
+        auto evit = t_events.find(c->device);
+        if (evit == t_events.end()) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            BZ_HIP(hipEventCreate(&e0));
+            if (hipEventCreate(&e1) != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                return fail(BZ_EDEVICE, "hipEventCreate");
+            }
+            evit = t_events.emplace(c->device, std::make_pair(e0, e1)).first;
         }
-        evit = t_events.emplace(c->device, std::make_pair(e0, e1)).first;
+        ev0 = evit->second.first;
+        ev1 = evit->second.second;
     }
-    const hipEvent_t ev0 = evit->second.first, ev1 = evit->second.second;
 
     uint32_t U = n - k + 1, L = 1, Lcert = 1;
     Best best;
@@ -619,8 +649,9 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     // starts over at a window's start; every earlier launch has finished by then.
     std::map<PlanKey, size_t> on_device;
     size_t rects_used = 0;
-    PinnedWords pinned;
-    unsigned long long *words = pinned.get();               // read-back of a window
+    std::optional<PinnedWords> pinned;
+    if (!na) pinned.emplace();
+    unsigned long long *words = na ? na->host : pinned->get();   // read-back of a window
     char *stage = (char *)words + kChainBytes;             // uploads of a window
     std::map<std::pair<uint32_t, uint32_t>, bz::SchedPlan> splans;            // (g, slots) -> prefix tasks
     struct DevBuf {
@@ -669,7 +700,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 bz::LevelPlan p;
                 if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
                     return fail(BZ_ELIMIT, err);
-                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "too many rectangles in one level");
+                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "a level's tiling needs more than the workspace's 16384 rectangles");
                 plans[t.key] = std::move(p);
             }
             t.plan = &plans[t.key];
@@ -796,7 +827,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 const size_t lds = bz::enum_lds_bytes(k, t.g, t.W);
                 const uint32_t grid =
                     (uint32_t)dc.cus * (uint32_t)bz::sched_blocks_per_cu(t.W, t.j >= m_f, stats, lds);
-                if (i == 0) BZ_HIP(hipEventRecord(ev0, st));
+                if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
                 BZ_HIP(bz::launch_sched(sa, t.W, t.j >= m_f, stats, grid, st));
             } else {
                 a.chain = d_state;
@@ -807,7 +838,7 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 const uint64_t blocks = (t.plan->total_tiles + 3) / 4;
                 const uint32_t grid =
                     (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
-                if (i == 0) BZ_HIP(hipEventRecord(ev0, st));
+                if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
                 BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
                 bz::ChainStep cs{};
                 cs.state = d_state;
@@ -822,12 +853,14 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
                 BZ_HIP(bz::launch_chain_step(cs, st));
             }
         }
-        BZ_HIP(hipEventRecord(ev1, st));
+        if (ev1) BZ_HIP(hipEventRecord(ev1, st));
         BZ_HIP(hipMemcpyAsync(words, ws + kWsChain, 128 + win.size() * kRecBytes, hipMemcpyDeviceToHost, st));
         BZ_HIP(hipStreamSynchronize(st));
-        float ms = 0.f;
-        BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        res->kernel_s += ms * 1e-3;
+        if (ev0) {
+            float ms = 0.f;
+            BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            res->kernel_s += ms * 1e-3;
+        }
 
         bool stopped = false;                  // L reached U at a level start inside the window
         for (size_t i = 0; i < win.size() && !done; ++i) {
@@ -938,6 +971,73 @@ bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
     if (status == BZ_OK) res->d = U;
     res->search_s = now_s() - t0;
     return status;
+}
+
+// The no-allocation search's per-device state: found once per device, then
+// shared (under its lock) by every call on that device.
+struct NoAllocDevice {
+    std::mutex mu;
+    bool ready = false;
+    NoAllocEnv env;
+    std::vector<unsigned long long> host;
+};
+
+constexpr size_t kBinomBytes = (size_t)bz::kBinomRows * (bz::kBinomT + 1) * sizeof(uint64_t);
+constexpr size_t kNoAllocWsOff = (kBinomBytes + 255) & ~(size_t)255;
+static_assert(kNoAllocWsOff + kWsBytes <= bz::kNoAllocScratchBytes,
+              "the scratch array holds the binomial table and one search's workspace");
+
+NoAllocDevice &noalloc_device(int dev) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<NoAllocDevice>> devs;
+    std::lock_guard<std::mutex> lk(mu);
+    auto &p = devs[dev];
+    if (!p) p.reset(new NoAllocDevice());
+    return *p;
+}
+
+// Set-up on the first call on a device, with that device current: the scratch
+// array's address on this device, the binomial table copied into it, and the
+// host read-back memory.
+bz_status noalloc_setup(int dev, NoAllocDevice &D) {
+    void *base = nullptr;
+    const hipError_t e = bz::noalloc_scratch_address(&base);
+    if (e != hipSuccess || !base)
+        return fail(BZ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    BZ_HIP(hipDeviceGetAttribute(&D.env.dc.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const std::vector<uint64_t> tab = bz::binom_table();
+    BZ_HIP(hipMemcpy(base, tab.data(), kBinomBytes, hipMemcpyHostToDevice));
+    D.env.dc.binom = (uint64_t *)base;
+    D.env.ws = (char *)base + kNoAllocWsOff;
+    D.host.assign(kPinnedBytes / 8, 0ull);
+    D.env.host = D.host.data();
+    D.ready = true;
+    return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bz_status bz_min_distance(bz_code *c, const bz_opts *o, bz_result *res) {
+    return min_distance_impl(c, o, res, nullptr);
+}
+
+bz_status bz_min_distance_noalloc(bz_code *c, const bz_opts *o, bz_result *res) {
+    if (!c || !res) return fail(BZ_EINVAL, "null argument");
+    if (!c->dev) return fail(BZ_EINVAL, "code prepared host-only (BZ_PREPARE_HOST_ONLY): submit it to a server");
+    if (o && o->workspace)
+        return fail(BZ_EINVAL, "the no-allocation search works in the library's scratch array: pass no workspace");
+    if (o && o->schedule != BZ_SCHED_TILES)
+        return fail(BZ_EINVAL, "schedules 1..8 need device memory for their tilings: use bz_min_distance");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(BZ_EDEVICE, "hipSetDevice");
+    NoAllocDevice &D = noalloc_device(c->device);
+    std::lock_guard<std::mutex> lk(D.mu);          // calls on one device share its array
+    if (!D.ready) {
+        const bz_status s = noalloc_setup(c->device, D);
+        if (s != BZ_OK) return s;
+    }
+    return min_distance_impl(c, o, res, &D.env);
 }
 
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,

@@ -23,6 +23,12 @@ struct DeviceConst {
     int cus = 0;
 };
 bz_status device_const(int dev, DeviceConst &out);
+// The binomial table as the kernels read it: kBinomRows x (kBinomT + 1) values.
+std::vector<uint64_t> binom_table();
+
+// Device address of the no-allocation search's scratch array on the current
+// device (bz_noalloc.hip).
+hipError_t noalloc_scratch_address(void **ptr);
 
 // Plans of levels 1, 2, ... for one (k, slots): appends one PlanEntry per level
 // (rect_off counted from rect_base + the rects already in `rects`) while

@@ -20,6 +20,10 @@ constexpr int kMaxHeadSide = 64;         // the head side is a 64-bit mask
 constexpr int kWaveSize = 64;
 constexpr int kBlock = 256;              // threads per work-group (4 waves)
 
+// Bytes of the device array that bz_min_distance_noalloc works in (one per
+// device): the binomial table, then a single search's workspace.
+constexpr size_t kNoAllocScratchBytes = BZ_NOALLOC_SCRATCH_BYTES;
+
 using HostRow = std::array<uint64_t, kHostWords>;
 
 // Combinations each lane keeps per head step, by 32-bit words per row: one
