@@ -6,6 +6,9 @@ returned must lie in the code with the asked weight.
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -78,12 +81,16 @@ def test_count_textbook(bz, name, builder, w, want):
 
 
 def test_count_plain128_minimum_weight(bz):
-    c = inputs.plain_code("plain128")
+    """plain128's minimum-weight codewords against the oracle's stored count and list."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workload_oracle.json")) as f:
+        ref = json.load(f)["count"]
+    c = inputs.plain_code("plain128", ref["seed"])
     code = bz.Code(c.G, c.n)
     got = bz.count_codewords(code, 0, cap=1 << 10)
     _say("plain128 A_d", got["count"], "hits", got["hits"], "levels", got["last_level"])
-    assert got["weight"] == 16 and got["count"] >= 1
-    assert len(got["codewords"]) == got["count"]
+    assert got["weight"] == ref["weight"] == 16
+    assert got["count"] == ref["count"]
+    assert got["codewords"].tolist() == ref["codewords"]
     for x in got["codewords"]:
         assert int(np.bitwise_count(x).sum()) == 16 and bf.in_code(x, c.G, c.n)
     code.close()
