@@ -304,10 +304,10 @@ def _search(fn, code, stats, level_stop, witness, max_level, slots_per_lane, hea
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.prefix = prefix
     wit = np.zeros(4, dtype=np.uint64)
-    st_buf = (LevelStat * stats_cap)()
+    st_buf = np.empty(stats_cap, dtype=_STAT_DTYPE)     # written by the library up to stats_len
     r = Result()
     r.witness = wit.ctypes.data_as(P(ctypes.c_uint64))
-    r.stats = st_buf
+    r.stats = st_buf.ctypes.data_as(P(LevelStat)) if stats_cap else None   # 0: no per-task records wanted
     r.stats_cap = stats_cap
     st = fn(code.handle, ctypes.byref(o), ctypes.byref(r))
     if st != BZ_OK and raise_on_error:
@@ -315,9 +315,9 @@ def _search(fn, code, stats, level_stop, witness, max_level, slots_per_lane, hea
     out = SearchResult(st, r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,
                        wit[: (code.n + 63) // 64].copy(), [], r.launches, r.prepare_s, r.search_s,
                        r.kernel_s)
-    for i in range(min(r.stats_len, stats_cap)):
-        s = st_buf[i]
-        out.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
+    m = min(r.stats_len, stats_cap)
+    if m:
+        out.stats = _stat_tuples(st_buf[:m])
     return out
 
 
@@ -339,10 +339,13 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
     o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile, tiles_per_task)
     res = (Result * cnt)()
     wits = np.zeros((cnt, 4), dtype=np.uint64)
-    stb = [(LevelStat * stats_cap)() for _ in range(cnt)]
+    # one buffer for every code's task records (stats_cap each; none when stats_cap is 0)
+    stb = np.zeros(cnt * stats_cap, dtype=_STAT_DTYPE) if stats_cap else None
+    wbase = wits.ctypes.data
+    sbase = stb.ctypes.data if stats_cap else 0
     for i in range(cnt):
-        res[i].witness = wits[i].ctypes.data_as(P(ctypes.c_uint64))
-        res[i].stats = stb[i]
+        res[i].witness = ctypes.cast(wbase + 32 * i, P(ctypes.c_uint64))
+        res[i].stats = ctypes.cast(sbase + i * stats_cap * _STAT_DTYPE.itemsize, P(LevelStat)) if stats_cap else None
         res[i].stats_cap = stats_cap
     per = (ctypes.c_int * cnt)()
     lib().bz_min_distance_batch(handles, cnt, ctypes.byref(o), res, per)
@@ -352,11 +355,23 @@ def min_distance_batch(codes, *, stats: bool = False, level_stop: bool = False, 
         o_ = SearchResult(per[i], r.d, r.lower_bound, r.upper_bound, r.last_level, r.combinations,
                           wits[i][: (codes[i].n + 63) // 64].copy(), [], r.launches, r.prepare_s,
                           r.search_s, r.kernel_s)
-        for t in range(min(r.stats_len, stats_cap)):
-            s = stb[i][t]
-            o_.stats.append((s.matrix, s.level, s.min_weight, s.count_at_min, s.combinations))
+        m = min(r.stats_len, stats_cap)
+        if m:
+            o_.stats = _stat_tuples(stb[i * stats_cap: i * stats_cap + m])
         outs.append(o_)
     return outs, [per[i] for i in range(cnt)]
+
+
+# the layout of bz_level_stat, for reading many records at once
+_STAT_DTYPE = np.dtype([("matrix", "<u2"), ("level", "<u2"), ("min_weight", "<u4"),
+                        ("count_at_min", "<u8"), ("combinations", "<u8")])
+assert _STAT_DTYPE.itemsize == ctypes.sizeof(LevelStat)
+
+
+def _stat_tuples(a) -> list:
+    """(matrix, level, min_weight, count_at_min, combinations) tuples of Python ints."""
+    return list(zip(a["matrix"].tolist(), a["level"].tolist(), a["min_weight"].tolist(),
+                    a["count_at_min"].tolist(), a["combinations"].tolist()))
 
 
 # ---------------------------------------------------------------- codewords of a given weight

@@ -71,7 +71,7 @@ using bz::now_s;
 // kRecWords words (key, counts and claim counter on separate 128-byte lines),
 // after the window's bounds (bz::ChainState).
 constexpr size_t kWsRecover = 384;     // flag, len (u32), codeword (4 x u64)
-constexpr size_t kWsIndices = 512;     // up to 256 u32 row indices
+constexpr size_t kWsIndices = 512;     // the witness's row indices: up to 384 u32 before kWsPreRows
 constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
 constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
@@ -81,6 +81,10 @@ constexpr size_t kWsChain = kWsRects + kMaxRects * sizeof(bz::Rect);   // ChainS
 constexpr size_t kChainBytes = 128 + kChainMax * kRecBytes;
 constexpr size_t kWsBytes = kWsChain + kChainBytes;
 static_assert(sizeof(bz::ChainState) <= 128, "bounds fit their line");
+static_assert(kWsRecover + 8 + bz::kHostWords * sizeof(uint64_t) <= kWsIndices, "flag, length and codeword fit");
+static_assert(kWsPreRows - kWsIndices >= (size_t)bz::kBinomT * sizeof(uint32_t),
+              "the recovered combination's row indices (g <= kBinomT) fit below the prefix rows");
+static_assert(kWsRects - kWsPreRows >= 64 * sizeof(uint32_t), "a prefix task's rows fit below the tilings");
 
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
@@ -140,7 +144,12 @@ struct Best {
 // ---------------------------------------------------------------- batched search
 
 constexpr uint64_t kBatchMaxComb = 1ull << 50;   // levels with C(k, g) beyond this get no plan
+static_assert(kBatchMaxComb <= (1ull << 55), "a task's count at the minimum fits the statistics word's 55 bits");
 constexpr uint64_t kBatchTargetTiles = 64;        // tiles per task aimed at by the planner
+// Head steps per tile at most. Finer caps cut a large task into more tiles
+// and cost more than they balance (4096-code batch kernel, measured: 0.78 s
+// at 4096, 0.83 s at 1024, 0.91 s at 512, 1.08 s at 256).
+constexpr uint32_t kBatchMaxHeads = 4096;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -152,6 +161,8 @@ struct BatchLayout {
     std::vector<unsigned long long> log_init;   // initial task-log entries
     unsigned long long log_tail = 0;             // initial log tail (head and next code start at 0)
     uint32_t done_init = 0, grid = 0, stats_total = 0;
+    uint32_t lds_k = 0, lds_g = 0;               // binomial table staged in LDS (0: none)
+    size_t lds_bytes = 0;
     uint64_t log_cap = 0;
     size_t off_codes = 0, off_states = 0, off_plans = 0, off_rects = 0, off_stats = 0,
            off_recover = 0, off_log = 0, off_done = 0, off_args = 0, total = 0;
@@ -170,7 +181,7 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         const uint32_t tiles = opt.tiles_per_task ? opt.tiles_per_task
                                : (bz::tuned_batch_tiles() ? bz::tuned_batch_tiles() : kBatchTargetTiles);
         const uint32_t gmax = bz::build_level_plans(k, slots, opt.heads_per_tile, tiles, kBatchMaxComb,
-                                                    0, Lo.plans, Lo.rects);
+                                                    0, Lo.plans, Lo.rects, kBatchMaxHeads);
         return plan_of[key] = {base, gmax};
     };
     for (uint32_t i = 0; i < count; ++i)
@@ -215,7 +226,19 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         Lo.states.push_back(S);
         Lo.log_cap += (uint64_t)d.nsets * std::max<uint32_t>(1, d.g_max) + 1;
     }
-    Lo.grid = (uint32_t)std::max(1, cus * bz::batch_blocks_per_cu(stats));
+    // the lane setup's binomials C(x, y), x < k, y <= g, in each work-group's
+    // LDS when the batch's largest table is small enough
+    uint32_t kmax = 0, gmax = 0;
+    for (const bz::BatchCode &d : Lo.codes) {
+        kmax = std::max(kmax, d.k);
+        gmax = std::max(gmax, d.g_max);
+    }
+    if (kmax && gmax && bz::batch_lds_bytes(kmax, gmax) <= bz::kBatchLdsMax) {
+        Lo.lds_k = kmax;
+        Lo.lds_g = gmax;
+        Lo.lds_bytes = bz::batch_lds_bytes(kmax, gmax);
+    }
+    Lo.grid = (uint32_t)std::max(1, cus * bz::batch_blocks_per_cu(stats, Lo.lds_bytes));
     size_t off = 0;
     Lo.off_codes = off; off = align256(off + count * sizeof(bz::BatchCode));
     Lo.off_states = off; off = align256(off + count * sizeof(bz::CodeState));
@@ -320,6 +343,8 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     b.done_count = (unsigned int *)(ws + Lo.off_done);
     b.cancel = (const uint32_t *)opt.cancel;
     b.ncodes = count;
+    b.lds_k = Lo.lds_k;
+    b.lds_g = Lo.lds_g;
     BZ_HIP(hipMemcpyAsync(ws + Lo.off_args, &b, sizeof(b), hipMemcpyHostToDevice, st));
 
     // one captured graph: the persistent search, then witness recovery
@@ -344,7 +369,7 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     BZ_HIP(hipEventRecord(e_ready, st));
     BZ_HIP(hipStreamWaitEvent(cs, e_ready, 0));
     BZ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t le = bz::launch_batch((const bz::BatchArgs *)(ws + Lo.off_args), Lo.grid, stats, cs);
+    hipError_t le = bz::launch_batch((const bz::BatchArgs *)(ws + Lo.off_args), Lo.grid, stats, Lo.lds_bytes, cs);
     hipError_t lr = (le == hipSuccess && !(opt.flags & BZ_F_NO_WITNESS)) ? bz::launch_batch_recover(b, cs) : hipSuccess;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess || lr != hipSuccess || ec != hipSuccess)
@@ -683,6 +708,8 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             else if (comb < bz::kSmallLevelComb) slots = std::min(slots, 8u);
         }
         if (slots == 16 && t.W > 4) return fail(BZ_EINVAL, "16 slots per lane need W <= 4");
+        if (stats && bz::binom_sat(k, g) >= (1ull << 55))
+            return fail(BZ_ELIMIT, "statistics mode keeps a task's count in 55 bits: C(k, g) >= 2^55");
         if (use_sched) {
             slots = bz::slots_for_w(t.W);               // the schedule kernel's fixed lane sums
             auto skey = std::make_pair(g, slots);

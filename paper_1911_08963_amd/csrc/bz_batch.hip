@@ -26,9 +26,10 @@
 // exponentially. Waves leave when every code is finished or the cancel word is
 // set.
 //
-// Atomics whose result the wave needs are issued by all 64 lanes on the same
-// word, with only lane 0 contributing (see wave_fetch_add64): no lane-dependent
-// branch surrounds the readfirstlane that broadcasts the result.
+// Atomics whose result the wave needs are issued once per wave: the helpers of
+// bz_wave.h narrow exec to the wave's first active lane around a single global
+// atomic, restore it, and readfirstlane hands the old value to every lane, so
+// no lane-dependent branch surrounds that readfirstlane.
 #include <hip/hip_runtime.h>
 
 #include "bz_internal.h"
@@ -63,35 +64,49 @@ __device__ __forceinline__ uint32_t certified_bound(uint32_t j, uint32_t g, uint
     return (j + 1) * (g + 1) + (m_f - j - 1) * g + (uint32_t)(e > 0 ? e : 0);
 }
 
+// A device-scope (relaxed) load: coherent across the XCDs' L2 caches.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One tile of a code's current task. The tile's combination count and
 // statistics go to the wave's own words (LDS), which the caller adds to the
 // task's once per claim.
 template <bool STATS>
 __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, uint64_t epoch, uint64_t tile,
-                                           uint32_t lane, cptr64 binom_c, unsigned long long *wave_words) {
+                                           uint32_t lane, cptr64 binom_c, const uint64_t *sb, uint32_t bt,
+                                           unsigned long long *wave_words) {
     const BatchCode &D = b.codes[code];
     TaskSlot *s = &b.state[code].slot[epoch & 1];
-    const uint32_t j = uni(s->j), g = uni(s->g);
+    // The slot's fields change with every task a code runs: device-scope
+    // loads read them where every XCD sees the publisher's stores, with no
+    // cache invalidation per claim (the release that published the epoch
+    // wrote them back first).
+    const uint32_t j = uni(ld_agent(&s->j)), g = uni(ld_agent(&s->g));
     const uint32_t k = uni(D.k), m_f = uni(D.m_f);
     const bool partial = j >= m_f;
     const uint32_t W = uni(partial ? D.W_partial : D.W_full);
     const uint32_t W_full = uni(D.W_full);
-    const uint32_t *rows = D.rows + (size_t)(partial ? m_f : j) * (k + 1) * W_full;
+    // uniform (readfirstlane): the head rows are then read with scalar loads
+    // into SGPRs, as in the single-code kernel, not with vector loads
+    const uint32_t *rows =
+        (const uint32_t *)uni64((uint64_t)(D.rows + (size_t)(partial ? m_f : j) * (k + 1) * W_full));
     TaskArgs a{};
     a.rows = rows;
     a.binom = b.binom;
-    a.rects = b.rects + uni(s->rect_off);
+    a.rects = b.rects + uni(ld_agent(&s->rect_off));
     a.key = &s->key;
     a.ncomb = wave_words;
     a.stats = wave_words + 1;
-    a.nrects = uni(s->nrects);
+    a.nrects = uni(ld_agent(&s->nrects));
     a.k = k;
     a.k_low = partial ? uni(D.k_m) : k;
     a.g = g;
-    a.heads_per_tile = uni(s->heads_per_tile);
-    a.total_tiles = uni64(s->tiles) & kCursorMask;
-    a.u_prev = uni(s->u_prev);
-    a.exit_at = uni(s->exit_at);
+    a.heads_per_tile = uni(ld_agent(&s->heads_per_tile));
+    a.total_tiles = uni64(ld_agent(&s->tiles)) & kCursorMask;
+    a.u_prev = uni(ld_agent(&s->u_prev));
+    a.exit_at = uni(ld_agent(&s->exit_at));
     if (a.exit_at) {
         unsigned long long kv = __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t cur = min((uint32_t)(kv >> kTileBits), a.u_prev);
@@ -99,15 +114,13 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     }
     cptr32 rc = (cptr32)rows;
     cptr_rect rp = (cptr_rect)a.rects;
-    const uint64_t *gb = b.binom;
-    constexpr uint32_t BT = kBinomT + 1;
     switch (W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
     case WW * 2:                                                                                      \
-        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane);    \
+        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, sb, bt, rp, tile, lane);    \
         break;                                                                                        \
     case WW * 2 + 1:                                                                                  \
-        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, gb, BT, rp, tile, lane);     \
+        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, sb, bt, rp, tile, lane);     \
         break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
@@ -244,11 +257,10 @@ __device__ __forceinline__ bool try_claim(const BatchArgs &b, uint32_t code, uin
     if ((tw0 >> kEpochShift) != e0 || (w0 & kCursorMask) >= (tw0 & kCursorMask)) return false;
     const uint64_t T0 = tw0 & kCursorMask;
     const uint64_t K = T0 >= kClaim8 ? 8 : (T0 >= kClaim4 ? 4 : (T0 >= kClaim2 ? 2 : 1));
-    // acquire without release: the fence after the fetch-add pairs with the
-    // release store that published this epoch (the task's slot is written
-    // before it), and the wave publishes nothing by claiming
+    // relaxed: the claimer reads the task's slot with device-scope loads
+    // (batch_tile), published before this epoch by a release store, and
+    // publishes nothing by claiming
     const unsigned long long w = wave_fetch_add64_relaxed(&S->cursor, K);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint64_t e = w >> kEpochShift, t = w & kCursorMask;
     if (e == kDoneEpoch) return false;
     const unsigned long long tw =
@@ -436,13 +448,29 @@ __device__ bool serve_start(const ServeArgs &sv, uint64_t ticket, uint32_t lane)
 // The persistent loop shared by the batch (a fixed set of codes, started
 // through a counter) and the server (requests published while it runs,
 // started by the wave holding their ticket).
-template <bool STATS, bool SERVE>
+template <bool STATS, bool SERVE, bool LDS_BINOM>
 __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *sv) {
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
     cptr64 binom_c = (cptr64)b.binom;
+    // The lane setup's binomials: from the work-group's LDS when the launch
+    // staged them there (they do not depend on the code), else from memory.
+    const uint64_t *sb = b.binom;
+    uint32_t bt = kBinomT + 1;
+    if (LDS_BINOM) {
+        extern __shared__ uint64_t sbin_lds[];
+        const uint32_t bk = b.lds_k, bg = b.lds_g;
+        bt = bg + 1;
+        for (uint32_t i = threadIdx.x; i < (bk + 1) * bt; i += blockDim.x) {
+            const uint32_t x = i / bt, y = i - x * bt;
+            sbin_lds[i] = b.binom[x * (kBinomT + 1) + y];
+        }
+        __syncthreads();
+        sb = sbin_lds;
+    }
     constexpr uint32_t kNone = 0xffffffffu;
     constexpr uint64_t kNoTicket = ~0ull;
     uint32_t cur = kNone;                              // the code this wave owns or helps
+    uint32_t fenced = kNone;                           // serving: the last request this wave acquired
     uint32_t idle = 0;                                 // consecutive rounds without work
     uint64_t ticket = kNoTicket;                       // serving: the request this wave will start
     uint64_t spread = uni64(((uint64_t)blockIdx.x << 8) ^ (threadIdx.x >> 6) ^ 0x9e3779b97f4a7c15ull);
@@ -565,6 +593,14 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             continue;
         }
         idle = 0;
+        if (SERVE && code != fenced) {
+            // a request's code description, rows and plan tables are written
+            // while the server runs: a wave acquires once before its first
+            // tile of each request (the acquire pairs with the release that
+            // published the request's first task)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            fenced = code;
+        }
         // the claim's count and statistics: the wave's LDS words, then one
         // atomic each on the task's words before the completion count
         if (lane == 0) {
@@ -572,7 +608,7 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
             wave_words[wv][1] = ~0ull;
         }
         for (uint64_t i = 0; i < count; ++i)
-            batch_tile<STATS>(b, code, epoch, tile + i, lane, binom_c, wave_words[wv]);
+            batch_tile<STATS>(b, code, epoch, tile + i, lane, binom_c, sb, bt, wave_words[wv]);
         TaskSlot *s = &b.state[code].slot[epoch & 1];
         if (lane == 0 && wave_words[wv][0]) {
             atomicAdd(&s->ncomb, wave_words[wv][0]);
@@ -581,23 +617,35 @@ __device__ __forceinline__ void queue_loop(const BatchArgs &b, const ServeArgs *
                 stats_merge(&s->stats, (uint32_t)(sw >> kCountBits), sw & kCountMask);
             }
         }
-        const uint64_t T = uni64(s->tiles) & kCursorMask;
-        const unsigned long long prev = wave_fetch_add64(&s->completed, count, lane);
-        if (prev + count == T) batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
+        const uint64_t T = uni64(ld_agent(&s->tiles)) & kCursorMask;
+        // The claim's count and statistics (atomics) are performed before the
+        // completion count; the wave has no plain stores to publish (its
+        // words are in LDS), so no cache write-back is needed.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const unsigned long long prev = wave_fetch_add64_relaxed(&s->completed, count);
+        if (prev + count == T) {
+            // the last wave reads the code's state the previous advance wrote
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            batch_advance<STATS, SERVE>(b, sv, code, epoch, lane);
+        }
     }
 }
 
 // The arguments of both persistent kernels live in device memory: passed by
 // value, their address (taken by the rare paths) would force a copy into
 // per-lane scratch.
-template <bool STATS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bz_batch_kernel(const BatchArgs *__restrict__ b) {
-    queue_loop<STATS, false>(*b, nullptr);
+// The batch kernel's register budget: at least 3 waves per SIMD. Forcing 4
+// or 5 made the 4096-code batch slower (0.78 s kernel at 3, 0.81 s at 4,
+// 0.84 s at 5: spilled registers in the wider row variants).
+template <bool STATS, bool LDS_BINOM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bz_batch_kernel(
+    const BatchArgs *__restrict__ b) {
+    queue_loop<STATS, false, LDS_BINOM>(*b, nullptr);
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(kBlock) void bz_serve_kernel(const ServeArgs *__restrict__ sv) {
-    queue_loop<STATS, true>(sv->b, sv);
+    queue_loop<STATS, true, false>(sv->b, sv);
 }
 
 // A finished request: its statistics and witness (found by this wave in the
@@ -770,13 +818,16 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
 }
 
 template <bool STATS>
-static hipError_t launch_batch_t(const BatchArgs *b, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((bz_batch_kernel<STATS>), dim3(grid), dim3(kBlock), 0, st, b);
+static hipError_t launch_batch_t(const BatchArgs *b, uint32_t grid, size_t lds, hipStream_t st) {
+    if (lds)
+        hipLaunchKernelGGL((bz_batch_kernel<STATS, true>), dim3(grid), dim3(kBlock), lds, st, b);
+    else
+        hipLaunchKernelGGL((bz_batch_kernel<STATS, false>), dim3(grid), dim3(kBlock), 0, st, b);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, hipStream_t st) {
-    return stats ? launch_batch_t<true>(b, grid, st) : launch_batch_t<false>(b, grid, st);
+hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, size_t lds_bytes, hipStream_t st) {
+    return stats ? launch_batch_t<true>(b, grid, lds_bytes, st) : launch_batch_t<false>(b, grid, lds_bytes, st);
 }
 
 template <bool STATS>
@@ -796,10 +847,15 @@ int serve_blocks_per_cu(bool stats) {
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-int batch_blocks_per_cu(bool stats) {
+int batch_blocks_per_cu(bool stats, size_t lds) {
     int n = 0;
-    hipError_t e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<true>, kBlock, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<false>, kBlock, 0);
+    hipError_t e;
+    if (lds)
+        e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<true, true>, kBlock, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<false, true>, kBlock, lds);
+    else
+        e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<true, false>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bz_batch_kernel<false, false>, kBlock, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 

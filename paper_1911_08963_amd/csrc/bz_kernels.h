@@ -163,7 +163,10 @@ struct BatchArgs {
     unsigned int *done_count;
     const uint32_t *cancel;
     uint64_t log_cap;             // ring size of the log, a power of two (entry q at q & (log_cap - 1))
-    uint32_t ncodes, _pad[3];
+    uint32_t ncodes;
+    // binomials C(x, y), x <= lds_k, y <= lds_g, staged in each work-group's
+    // LDS when the launch gives it room for them (0 = read from binom)
+    uint32_t lds_k, lds_g, _pad;
 };
 
 // ---- serving: a resident search that admits codes while it runs
@@ -224,9 +227,14 @@ hipError_t launch_serve(const ServeArgs *sv, uint32_t grid, bool stats, hipStrea
 int serve_blocks_per_cu(bool stats);
 
 // b: the arguments in device memory (read while the kernel runs).
-hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, hipStream_t st);
+// lds_bytes: the binomial table's LDS (batch_lds_bytes of the args' lds_k, lds_g; 0 = none).
+hipError_t launch_batch(const BatchArgs *b, uint32_t grid, bool stats, size_t lds_bytes, hipStream_t st);
 hipError_t launch_batch_recover(const BatchArgs &b, hipStream_t st);
-int batch_blocks_per_cu(bool stats);
+int batch_blocks_per_cu(bool stats, size_t lds_bytes);
+// LDS bytes of the binomial table C(x, y), x <= k, y <= g.
+constexpr size_t batch_lds_bytes(uint32_t k, uint32_t g) { return (size_t)(k + 1) * (g + 1) * sizeof(uint64_t); }
+// Largest table staged in LDS: with more the work-groups a CU holds would drop.
+constexpr size_t kBatchLdsMax = 24 * 1024;
 
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st);

@@ -39,6 +39,7 @@ using bz::fail;
 using bz::now_s;
 
 constexpr uint64_t kServeMaxComb = 1ull << 50;  // levels with C(k, g) beyond this get no plan
+static_assert(kServeMaxComb <= (1ull << 55), "a task's count at the minimum fits the statistics word's 55 bits");
 constexpr uint32_t kMaxPlans = 4096;            // distinct (k, slots) plans per server
 constexpr uint32_t kPlanEntries = 1u << 17;     // PlanEntry table (4 MiB)
 constexpr uint32_t kPlanRects = 1u << 19;       // Rect table (40 MiB)

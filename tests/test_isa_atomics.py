@@ -26,7 +26,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 @pytest.mark.skipif(not os.path.exists(HIPCC) and not shutil.which("hipcc"), reason="hipcc not installed")
 @pytest.mark.parametrize("source,pattern,count", [
-    ("bz_batch.hip", r"^(_ZN2bz\d+bz_(?:batch|serve)_kernel\w+):", 4),
+    ("bz_batch.hip", r"^(_ZN2bz\d+bz_(?:batch|serve)_kernel\w+):", 6),
     ("bz_sched.hip", r"^(_ZN2bz\d+bz_sched_kernel\w+):", 32),
 ])
 def test_persistent_kernel_atomics_are_single_lane(tmp_path, source, pattern, count):
