@@ -81,7 +81,42 @@ WORKLOADS = {
 }
 
 
-def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True) -> dict:
+def _oracle_code(args):
+    """One complete oracle search (run in a worker process): (d, combinations, seconds)."""
+    import oracle
+    G, n = args
+    t = time.perf_counter()
+    r = oracle.min_distance(G, n)
+    return r.d, r.combinations, time.perf_counter() - t
+
+
+def cpu_codes_rate(pool, nprocs: int, codes, gpu_d, gpu_comb, max_comb: float, seconds: float) -> dict:
+    """The oracle on a bounded sample of a workload's codes: complete searches, in the
+    workload's order, of the codes whose search enumerates at most max_comb combinations
+    (one code per process, nprocs at a time), until `seconds` have passed. Each d is
+    checked against the GPU's."""
+    import itertools
+    sample = [(c.G, c.n, d) for c, d, cb in zip(codes, gpu_d, gpu_comb) if cb <= max_comb]
+    it = iter(sample)
+    t0 = time.perf_counter()
+    done = comb = 0
+    while time.perf_counter() - t0 < seconds:
+        chunk = list(itertools.islice(it, nprocs * 2))
+        if not chunk:
+            break
+        for (G, n, d), (od, cb, _) in zip(chunk, pool.map(_oracle_code, [(G, n) for G, n, _ in chunk])):
+            assert od == d, "oracle and GPU disagree on d"
+            done += 1
+            comb += cb
+    wall = time.perf_counter() - t0
+    return {"codes": done, "combinations": comb, "wall_s": wall, "cores": nprocs,
+            "comb_per_s": comb / wall, "codes_per_s_on_sample": done / wall,
+            "sample": f"complete oracle searches of the first {done} codes, in workload order, whose search "
+                      f"enumerates at most {max_comb:.0e} combinations, {nprocs} processes (one code each)"}
+
+
+def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True, pool=None,
+                     nprocs: int = 1, cpu_seconds: float = 10.0) -> dict:
     """codes/s of one bz_min_distance_batch call against bz_min_distance per code."""
     import torch
 
@@ -110,10 +145,23 @@ def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True) 
     mism = sum(1 for a, b in zip(outs, plain) if a.d != b.d)
     assert mism == 0, f"{mism} codes differ between batched and plain"
     comb = sum(o.combinations for o in outs)
-    print(f"batch: {len(objs)} codes ({drawn} drawn, setup {setup:.1f} s): batched {tb:.3f} s, "
-          f"plain {tp:.3f} s", file=sys.stderr, flush=True)
+    # algorithmic work: 2W + 1 int32 operations per combination, W of each task's matrix
+    ops = sum(s[4] * (2 * (o_.W_full if s[0] < o_.num_full else o_.W_partial) + 1)
+              for o_, r in zip(objs, outs) for s in r.stats)
+    assert sum(s[4] for r in outs for s in r.stats) == comb, "per-task records cover every combination"
+    kern = outs[0].kernel_s
+    print(f"batch: {len(objs)} codes ({drawn} drawn, setup {setup:.1f} s): batched {tb:.3f} s "
+          f"(kernel {kern:.3f} s), plain {tp:.3f} s", file=sys.stderr, flush=True)
     for o in objs:
         o.close()
+    cpu = None
+    if pool is not None:
+        cpu = cpu_codes_rate(pool, nprocs, kept, [o.d for o in outs], [o.combinations for o in outs],
+                             2e8, cpu_seconds)
+        cpu["codes_per_s_at_workload_mean"] = cpu["comb_per_s"] / (comb / len(outs))
+        cpu["kind"] = "oracle"
+        print(f"batch cpu baseline: {cpu['codes']} codes, {cpu['comb_per_s']:.3e} comb/s on {nprocs} cores",
+              file=sys.stderr, flush=True)
     return {
         "workload": "batched: random binary codes, n ~ U{48..160}, rho ~ U[0.33, 0.6], k = round(n rho), "
                     "seeds 1000000+i, kept when the estimated cost is <= cap",
@@ -121,6 +169,13 @@ def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True) 
         "batched_s": tb, "plain_s": tp, "tiles_per_task": tiles if tiles else 64,
         "batched_codes_per_s": len(objs) / tb, "plain_codes_per_s": len(objs) / tp,
         "speedup": tp / tb, "batched_combinations_per_s": comb / tb,
+        "kernel_s": kern,
+        "roofline": {"bound": "alu", "kernel": "bz_batch_kernel (one graph launch, with witness recovery)",
+                     "ops": ops, "ops_per_combination": ops / comb,
+                     "achieved": ops / kern / 1e12, "peak": PEAK_INT32_TOPS,
+                     "unit": "TOP/s (int32 lane operations)", "frac": ops / kern / 1e12 / PEAK_INT32_TOPS,
+                     "frac_of_wall": ops / tb / 1e12 / PEAK_INT32_TOPS},
+        "cpu_baseline": cpu,
         "d_histogram": {str(d): int(n) for d, n in zip(*np.unique([o.d for o in outs], return_counts=True))},
     }
 
@@ -152,22 +207,35 @@ def schedules_comparison(bz, c, workload: str, d: int) -> dict:
 
 
 def time_to_d_small(bz, inputs, name: str, runs: int) -> dict:
-    """Median time-to-d of a small plain workload over many runs (prepare and search split)."""
+    """Median time-to-d of a small plain workload over many runs (prepare and search split),
+    with its int32 VALU roofline figures: (2W+1) x combinations over the median kernel time
+    (the search's launches, timed with HIP events) and over the median time-to-d."""
     c = inputs.plain_code(name)
-    tot, prep, srch, ds = [], [], [], set()
+    tot, prep, srch, kern, ds, combs = [], [], [], [], set(), set()
+    W = 0
     for _ in range(runs):
         t = time.perf_counter()
         code = bz.Code(c.G, c.n)
         r = bz.min_distance(code)
         tot.append(time.perf_counter() - t)
+        W = code.W_full
         prep.append(r.prepare_s)
         srch.append(r.search_s)
+        kern.append(r.kernel_s)
         ds.add(r.d)
+        combs.add(r.combinations)
         code.close()
-    assert len(ds) == 1
+    assert len(ds) == 1 and len(combs) == 1
     med = lambda x: float(np.median(x))
+    comb = combs.pop()
+    ops = comb * (2 * W + 1)
     return {"workload": name, "n": c.n, "k": c.k, "d": ds.pop(), "runs": runs, "median_s": med(tot),
-            "prepare_s": med(prep), "search_s": med(srch)}
+            "prepare_s": med(prep), "search_s": med(srch), "kernel_s": med(kern), "combinations": comb,
+            "roofline": {"bound": "alu", "kernel": "bz_enum_kernel", "ops_per_combination": 2 * W + 1,
+                         "achieved": ops / med(kern) / 1e12, "peak": PEAK_INT32_TOPS,
+                         "unit": "TOP/s (int32 lane operations)",
+                         "frac": ops / med(kern) / 1e12 / PEAK_INT32_TOPS,
+                         "frac_of_time_to_d": ops / med(tot) / 1e12 / PEAK_INT32_TOPS}}
 
 
 def cpu_oracle_rate(c, max_level: int, min_seconds: float, pool=None, nprocs: int = 1):
@@ -186,6 +254,63 @@ def cpu_oracle_rate(c, max_level: int, min_seconds: float, pool=None, nprocs: in
         reps += 1
     dt = time.perf_counter() - t
     return done / dt, done, reps, dt
+
+
+# The paper's own end-to-end figures (Table 2, Sec. 4.6), for context only: its
+# codes are not available, and its hardware is a 2009-era CPU cluster.
+PAPER_CONTEXT = {
+    "source": "arXiv:1911.08963, Table 2 (Sec. 4.6): time to d, seconds",
+    "mat023 [232,51,61]": {"Guava 3.12, 1 core": 456413.2, "Magma 2.22-3, 1 core": 503984.2,
+                           "Magma, 6 cores": 85341.1, "paper's D-Lex, 288 cores": 282.6},
+    "mat015 [150,77,17]": {"Guava 3.12, 1 core": 40804.3, "Magma 2.22-3, 1 core": 53052.9,
+                           "Magma, 6 cores": 9562.8, "paper's D-Lex, 288 cores": 38.9},
+    "summary": "about 5 days with GAP/Guava against under 5 minutes on 288 cores (24 nodes of 2 Xeon X5560, "
+               "InfiniBand) for mat023; the codes are not public, so this build measures random codes",
+}
+# Oracle process pools are sized to the CPUs the GPU machine grants one GPU (16), whatever
+# os.cpu_count() reports there; a smaller host uses all its cores.
+CORES_NOTE = "oracle processes = min(16, os.cpu_count()): the GPU box grants one GPU 16 CPUs"
+
+
+def serving_runs(args, pool, nprocs) -> dict:
+    """The Poisson stream through the resident server (default: every arrival served, requests
+    over the cost cap limited to a level budget), then two shorter variants: an HBM budget that
+    binds admission, and a small codes_per_launch that forces kernel relaunches."""
+    from paper_1911_08963_amd import serving
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    sv = serving.run(args.serve_rate, args.serve_seconds, cost_cap=args.serve_cap, progress=say,
+                     keep_results=pool is not None)
+    sv["workload"] = ("serving: Poisson arrivals (seed 7), request i a random binary code from seed "
+                      "2000000+i with n ~ U{64..192}, k ~ U{ceil(n/3)..floor(n/2)}; every arrival is "
+                      "served; requests whose estimated cost exceeds cost_cap run only the levels that fit "
+                      "bound_budget and return their certified bounds (status ELIMIT)")
+    sv["roofline"] = {"bound": "alu", "kernel": "bz_serve_kernel (resident for the whole stream)",
+                      "achieved": sv["lane_ops"] / sv["wall_s"] / 1e12, "peak": PEAK_INT32_TOPS,
+                      "unit": "TOP/s (int32 lane operations)",
+                      "frac": sv["lane_ops"] / sv["wall_s"] / 1e12 / PEAK_INT32_TOPS,
+                      "note": "over the stream's wall time: bounded by the offered load, not the kernel"}
+    results = sv.pop("results", None)
+    if pool is not None and results:
+        from paper_1911_08963_amd import inputs
+        idx = sorted(i for i, r in results.items() if r.status == 0)
+        codes = [inputs.serve_code(i) for i in idx]
+        cpu = cpu_codes_rate(pool, nprocs, codes, [results[i].d for i in idx],
+                             [results[i].combinations for i in idx], 2e8, args.cpu_min_seconds)
+        exact_comb = sum(results[i].combinations for i in idx)
+        cpu["codes_per_s_at_workload_mean"] = cpu["comb_per_s"] / (exact_comb / max(1, len(idx)))
+        cpu["kind"] = "oracle"
+        sv["cpu_baseline"] = cpu
+        say(f"serving cpu baseline: {cpu['codes']} codes, {cpu['comb_per_s']:.3e} comb/s on {nprocs} cores")
+    if args.serve_variants_seconds > 0:
+        sv["variants"] = {}
+        for name, kw in (("hbm_budget_binding", {"hbm_budget": 256 * 1024}),
+                         ("codes_per_launch_256", {"codes_per_launch": 256})):
+            v = serving.run(args.serve_rate, args.serve_variants_seconds, cost_cap=args.serve_cap,
+                            progress=say, **kw)
+            sv["variants"][name] = {k: v[k] for k in (
+                "arrivals", "exact", "bounded", "errors", "deferred_submits", "hbm_budget", "codes_per_launch",
+                "p50_ms", "p99_ms", "p50_ms_exact", "p99_ms_exact", "codes_per_s", "duration_s")}
+    return sv
 
 
 def main():
@@ -210,7 +335,11 @@ def main():
                     help="length of the Poisson serving stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-cap", type=float, default=1e11,
-                    help="serving admission: reject requests whose estimated cost exceeds this")
+                    help="serving: requests whose estimated cost exceeds this run only the levels within "
+                         "a 1e10-combination budget and return bounds")
+    ap.add_argument("--serve-variants-seconds", type=float, default=15.0,
+                    help="length of each of the two serving variants (binding HBM budget, kernel "
+                         "relaunch every 256 requests); 0 skips them")
     ap.add_argument("--no-count", dest="count_min_weight", action="store_false",
                     help="skip counting the workload's minimum-weight codewords")
     ap.add_argument("--no-schedules", dest="schedules", action="store_false",
@@ -342,21 +471,19 @@ def main():
         },
         "autotune": tuned,
     }
-    rate = ctypes.c_double()
-    secs = ctypes.c_double()
-    if bz.lib().bz_debug_valu_rate(0, ctypes.byref(rate), ctypes.byref(secs)) == 0:
-        line["roofline"]["measured_peak"] = rate.value / 1e12
-        line["roofline"]["frac_of_measured_peak"] = achieved / (rate.value / 1e12)
-        print(f"measured int32 VALU rate {rate.value / 1e12:.2f} TOP/s ({secs.value * 1e3:.1f} ms probe)",
-              file=sys.stderr, flush=True)
+    line["paper_context"] = PAPER_CONTEXT
     line["time_to_d_s"] = {"plain192": {
         "workload": args.workload, "n": c.n, "k": c.k, "d": d, "runs": args.steps,
         "median_s": float(np.median([r.prepare_s + r.search_s for r in results])),
         "prepare_s": float(np.median([r.prepare_s for r in results])),
         "search_s": float(np.median([r.search_s for r in results]))}}
+    line["roofline_by_config"] = {"plain192": dict(line["roofline"], frac_of_time_to_d=ops / wall / 1e12 /
+                                                   PEAK_INT32_TOPS)}
     if args.small_runs:
         for name in ("plain40", "plain128"):
-            line["time_to_d_s"][name] = time_to_d_small(bz, inputs, name, args.small_runs)
+            t = time_to_d_small(bz, inputs, name, args.small_runs)
+            line["roofline_by_config"][name] = t.pop("roofline")
+            line["time_to_d_s"][name] = t
     if args.count_min_weight:
         # the number of codewords of weight d: the search continued until the
         # certified bound passes d, weight-d sums collected and de-duplicated
@@ -372,15 +499,12 @@ def main():
     if args.schedules and args.workload in SCHED_PREFIX:
         line["schedules"] = schedules_comparison(bz, c, args.workload, d)
     if args.batch:
-        line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune)
+        line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune,
+                                         pool, nprocs, args.cpu_min_seconds)
+        line["roofline_by_config"]["batch"] = line["batch"]["roofline"]
     if args.serve_seconds > 0:
-        from paper_1911_08963_amd import serving
-        sv = serving.run(args.serve_rate, args.serve_seconds, cost_cap=args.serve_cap,
-                         progress=lambda m: print(m, file=sys.stderr, flush=True))
-        sv["workload"] = ("serving: Poisson arrivals (seed 7), request i a random binary code from seed "
-                          "2000000+i with n ~ U{64..192}, k ~ U{ceil(n/3)..floor(n/2)}; requests whose "
-                          "estimated cost exceeds cost_cap are rejected at admission")
-        line["serving"] = sv
+        line["serving"] = serving_runs(args, pool, nprocs)
+        line["roofline_by_config"]["serving"] = line["serving"]["roofline"]
     if not args.no_cpu:
         v1, n1, r1, t1 = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds)
         vp, np_, rp, tp = cpu_oracle_rate(c, args.cpu_max_level, args.cpu_min_seconds, pool, nprocs)
@@ -411,6 +535,7 @@ def main():
         }
         line["cpu_baseline"] = {
             "value": vp, "unit": "combinations/s", "cores": nprocs, "kind": "oracle",
+            "cores_note": CORES_NOTE,
             "sample": f"C oracle on the same code, levels 1-{args.cpu_max_level} of all 3 Gamma_j, "
                       f"in {nprocs} processes splitting each level's lex prefixes cyclically (Alg. 3); "
                       f"{rp} repetitions ({np_} combinations in {tp:.1f} s)",

@@ -94,7 +94,10 @@ typedef struct {
     uint32_t W_partial;     /* the same for Gamma_m (0 if absent)                    */
 } bz_code_info;
 
-/* set_of_column (nullable, n entries): index j of the set holding column c, or -1. */
+/* The shape of a prepared code: m_f and k_m of Sec. 2.1 (the number of
+ * disjoint full-rank information sets and the rank of the leftover columns),
+ * and the 32-bit words per device row. set_of_column (nullable, n entries):
+ * index j of the set holding column c, or -1. */
 bz_status bz_code_get_info(const bz_code *c, bz_code_info *out, int32_t *set_of_column);
 
 /* Host copy of Gamma_j (k rows of ld_words uint64, original column order). */
@@ -174,7 +177,10 @@ typedef struct {
     double kernel_s;            /* summed device time of the enumeration launches            */
 } bz_result;
 
-/* Device bytes the library needs for these codes under these options. */
+/* Device bytes the library needs for these codes under these options (the
+ * workspace of bz_min_distance with count 0 or 1, of bz_min_distance_batch
+ * otherwise). A property of this library's layout; the paper has no
+ * counterpart. Errors: EINVAL, EDEVICE. */
 bz_status bz_workspace_bytes(bz_code *const *codes, uint32_t count, const bz_opts *o, size_t *bytes);
 
 /* Alg. 1 on one code, the check after every Gamma_j by default.
@@ -209,9 +215,15 @@ bz_status bz_min_distance(bz_code *code, const bz_opts *o, bz_result *res);
 #define BZ_NOALLOC_SCRATCH_BYTES 1572864u
 bz_status bz_min_distance_noalloc(bz_code *code, const bz_opts *o, bz_result *res);
 
-/* Many codes at once: one persistent launch drains a device queue of
- * (code, Gamma_j, g, tile) work for all of them. res[i] and per_code[i] belong
- * to codes[i]. Returns the first per-code error, or BZ_OK. */
+/* Many codes at once: Alg. 1 (with the per-Gamma check of Sec. 2.2) for each
+ * code, all in one persistent launch that drains a device queue of
+ * (code, Gamma_j, g, tile) work; the wave that completes a task does that
+ * code's bookkeeping and publishes its next task (the dynamic coordinator and
+ * workers of Sec. 3.2, on the waves of one GPU; the paper runs one code at a
+ * time). Each code's result equals bz_min_distance's for it. res[i] and
+ * per_code[i] belong to codes[i]. Returns the first per-code error, or BZ_OK.
+ * o->workspace, when given, must hold bz_workspace_bytes for these codes
+ * (ENOMEM otherwise). */
 bz_status bz_min_distance_batch(bz_code *const *codes, uint32_t count, const bz_opts *o,
                                 bz_result *res, bz_status *per_code);
 

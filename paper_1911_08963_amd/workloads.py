@@ -66,3 +66,16 @@ def select(draw, info, count: int, cap: float, max_draws: int = 1_000_000):
             kept.append(c)
             costs.append(est)
     return kept, i, costs
+
+
+def level_within(n: int, k: int, m_f: int, k_m: int, budget: float) -> int:
+    """The deepest level g >= 1 whose tasks (every Gamma_j at levels 1..g) enumerate at most
+    budget combinations in all: a request limited to it stays within that budget."""
+    nsets = m_f + (1 if k_m else 0)
+    total, g = 0, 0
+    while g < k:
+        nxt = total + nsets * math.comb(k, g + 1)
+        if nxt > budget:
+            break
+        total, g = nxt, g + 1
+    return max(g, 1)

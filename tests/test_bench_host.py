@@ -48,3 +48,24 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_paper_context_figures():
+    # Table 2 (Sec. 4.6): mat023 with GAP/Guava on one core against the paper's D-Lex on 288 cores
+    m23 = bench.PAPER_CONTEXT["mat023 [232,51,61]"]
+    assert m23["Guava 3.12, 1 core"] == 456413.2 and m23["paper's D-Lex, 288 cores"] == 282.6
+    assert bench.PAPER_CONTEXT["mat015 [150,77,17]"]["paper's D-Lex, 288 cores"] == 38.9
+
+
+def test_serving_level_budget():
+    import math
+
+    from paper_1911_08963_amd import workloads
+    for n, k, m_f, k_m in ((192, 96, 1, 40), (128, 64, 2, 0), (100, 45, 2, 10), (64, 32, 1, 0)):
+        nsets = m_f + (1 if k_m else 0)
+        for budget in (1e6, 1e9, 1e10):
+            g = workloads.level_within(n, k, m_f, k_m, budget)
+            cost = lambda lv: sum(nsets * math.comb(k, x) for x in range(1, lv + 1))
+            assert g >= 1
+            assert g == 1 or cost(g) <= budget
+            assert g == k or cost(g + 1) > budget
