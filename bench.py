@@ -116,7 +116,7 @@ def cpu_codes_rate(pool, nprocs: int, codes, gpu_d, gpu_comb, max_comb: float, s
 
 
 def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True, pool=None,
-                     nprocs: int = 1, cpu_seconds: float = 10.0) -> dict:
+                     nprocs: int = 1, cpu_seconds: float = 10.0, plain: bool = True) -> dict:
     """codes/s of one bz_min_distance_batch call against bz_min_distance per code."""
     import torch
 
@@ -138,12 +138,14 @@ def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True, 
     torch.cuda.synchronize()
     tb = time.perf_counter() - t
     assert all(s == 0 for s in sts), "batched search failed"
-    t = time.perf_counter()
-    plain = [bz.min_distance(o) for o in objs]
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t
-    mism = sum(1 for a, b in zip(outs, plain) if a.d != b.d)
-    assert mism == 0, f"{mism} codes differ between batched and plain"
+    tp = float("nan")
+    if plain:
+        t = time.perf_counter()
+        plain_res = [bz.min_distance(o) for o in objs]
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        mism = sum(1 for a, b in zip(outs, plain_res) if a.d != b.d)
+        assert mism == 0, f"{mism} codes differ between batched and plain"
     comb = sum(o.combinations for o in outs)
     # algorithmic work: 2W + 1 int32 operations per combination, W of each task's matrix
     ops = sum(s[4] * (2 * (o_.W_full if s[0] < o_.num_full else o_.W_partial) + 1)
@@ -166,9 +168,9 @@ def batch_comparison(bz, inputs, count: int, cap: float, autotune: bool = True, 
         "workload": "batched: random binary codes, n ~ U{48..160}, rho ~ U[0.33, 0.6], k = round(n rho), "
                     "seeds 1000000+i, kept when the estimated cost is <= cap",
         "codes": len(objs), "drawn": drawn, "cost_cap": cap, "combinations": comb,
-        "batched_s": tb, "plain_s": tp, "tiles_per_task": tiles if tiles else 64,
-        "batched_codes_per_s": len(objs) / tb, "plain_codes_per_s": len(objs) / tp,
-        "speedup": tp / tb, "batched_combinations_per_s": comb / tb,
+        "batched_s": tb, "plain_s": tp if plain else None, "tiles_per_task": tiles if tiles else 64,
+        "batched_codes_per_s": len(objs) / tb, "plain_codes_per_s": len(objs) / tp if plain else None,
+        "speedup": tp / tb if plain else None, "batched_combinations_per_s": comb / tb,
         "kernel_s": kern,
         "roofline": {"bound": "alu", "kernel": "bz_batch_kernel (one graph launch, with witness recovery)",
                      "ops": ops, "ops_per_combination": ops / comb,
@@ -329,6 +331,10 @@ def main():
                     help="runs of the [40,20] and [128,64] workloads for their median time-to-d (0 skips)")
     ap.add_argument("--batch", type=int, default=4096,
                     help="codes in the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--no-batch-plain", dest="batch_plain", action="store_false",
+                    help="skip the per-code plain searches of the batch comparison (for profiling runs)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the int32 issue-rate probe and print its rate (for profiling runs)")
     ap.add_argument("--batch-cap", type=float, default=1e10,
                     help="keep batched-workload codes whose estimated cost is at most this")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -382,6 +388,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_ref_bytes": args.copy_ref, "launches": 3}), flush=True)
+        return
+    if args.valu_probe:
+        rate, secs = ctypes.c_double(), ctypes.c_double()
+        assert bz.lib().bz_debug_valu_rate(0, ctypes.byref(rate), ctypes.byref(secs)) == 0
+        print(json.dumps({"valu_probe_lane_ops_per_s": rate.value, "seconds": secs.value}), flush=True)
         return
     c = inputs.plain_code(args.workload)
     tuned = None
@@ -500,7 +511,7 @@ def main():
         line["schedules"] = schedules_comparison(bz, c, args.workload, d)
     if args.batch:
         line["batch"] = batch_comparison(bz, inputs, args.batch, args.batch_cap, args.autotune,
-                                         pool, nprocs, args.cpu_min_seconds)
+                                         pool, nprocs, args.cpu_min_seconds, args.batch_plain)
         line["roofline_by_config"]["batch"] = line["batch"]["roofline"]
     if args.serve_seconds > 0:
         line["serving"] = serving_runs(args, pool, nprocs)
