@@ -109,7 +109,9 @@ void bz_free(bz_code *c);
 enum {
     BZ_F_STATS = 1u,        /* record per-(Gamma_j, g) minimum and count; no exit inside a task */
     BZ_F_LEVEL_STOP = 2u,   /* check L >= U once per level (Alg. 1 as printed)                 */
-    BZ_F_NO_WITNESS = 4u    /* skip witness recovery                                           */
+    BZ_F_NO_WITNESS = 4u,   /* skip witness recovery                                           */
+    BZ_F_TASK_LAUNCHES = 8u /* bz_min_distance: one launch per task on every level (by default the
+                               levels of at most 2^31 sums run in one launch); EINVAL elsewhere  */
 };
 
 typedef struct {

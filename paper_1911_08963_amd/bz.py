@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libbz.so")
 
 BZ_OK, BZ_EINVAL, BZ_ERANK, BZ_ENOMEM, BZ_EDEVICE, BZ_ELIMIT, BZ_ECANCELED, BZ_EBUSY = \
     0, -1, -2, -3, -4, -5, -6, -7
-BZ_F_STATS, BZ_F_LEVEL_STOP, BZ_F_NO_WITNESS = 1, 2, 4
+BZ_F_STATS, BZ_F_LEVEL_STOP, BZ_F_NO_WITNESS, BZ_F_TASK_LAUNCHES = 1, 2, 4, 8
 # bz_opts.schedule: the equal-cost tiles (0) or the paper's eight distributed schedules
 SCHEDULES = {"tiles": 0, "D-Lex": 1, "D-Lex-2cm": 2, "D-Lle": 3, "D-Lle-2cm": 4,
              "S-Lex": 5, "S-Lex-Snc": 6, "S-Lle": 7, "S-Lle-Snc": 8}
@@ -270,17 +270,20 @@ def _opts(flags, max_level, stream, ws, cancel, slots, heads, tiles=0) -> Opts:
 def min_distance(code: Code, *, stats: bool = False, level_stop: bool = False,
                  witness: bool = True, max_level: int = 0, slots_per_lane: int = 0,
                  heads_per_tile: int = 0, stats_cap: int = 4096, stream=None,
-                 cancel=None, raise_on_error: bool = True, schedule=0, prefix: int = 0) -> SearchResult:
+                 cancel=None, raise_on_error: bool = True, schedule=0, prefix: int = 0,
+                 task_launches: bool = False) -> SearchResult:
     """bz_min_distance on the current torch stream, with a torch-allocated workspace.
 
     schedule: 0 / "tiles", or one of the paper's schedules by number (1..8) or
-    name ("D-Lex", ..., "S-Lle-Snc", see SCHEDULES) with its prefix size."""
+    name ("D-Lex", ..., "S-Lle-Snc", see SCHEDULES) with its prefix size.
+    task_launches: one launch per task on every level (BZ_F_TASK_LAUNCHES)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = stream if stream is not None else torch.cuda.current_stream(dev)
     ws = _workspace(dev, workspace_bytes())
     return _search(lib().bz_min_distance, code, stats, level_stop, witness, max_level, slots_per_lane,
-                   heads_per_tile, stats_cap, stream, ws, cancel, raise_on_error, schedule, prefix)
+                   heads_per_tile, stats_cap, stream, ws, cancel, raise_on_error, schedule, prefix,
+                   task_launches)
 
 
 def min_distance_noalloc(code: Code, *, stats: bool = False, level_stop: bool = False,
@@ -297,9 +300,9 @@ def min_distance_noalloc(code: Code, *, stats: bool = False, level_stop: bool = 
 
 
 def _search(fn, code, stats, level_stop, witness, max_level, slots_per_lane, heads_per_tile, stats_cap,
-            stream, ws, cancel, raise_on_error, schedule, prefix) -> SearchResult:
+            stream, ws, cancel, raise_on_error, schedule, prefix, task_launches=False) -> SearchResult:
     flags = (BZ_F_STATS if stats else 0) | (BZ_F_LEVEL_STOP if level_stop else 0) | \
-        (0 if witness else BZ_F_NO_WITNESS)
+        (0 if witness else BZ_F_NO_WITNESS) | (BZ_F_TASK_LAUNCHES if task_launches else 0)
     o = _opts(flags, max_level, stream.cuda_stream, ws, cancel, slots_per_lane, heads_per_tile)
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.prefix = prefix

@@ -79,7 +79,12 @@ constexpr uint32_t kChainMax = 32;
 constexpr size_t kRecBytes = bz::kRecWords * 8;
 constexpr size_t kWsChain = kWsRects + kMaxRects * sizeof(bz::Rect);   // ChainState, then the records
 constexpr size_t kChainBytes = 128 + kChainMax * kRecBytes;
-constexpr size_t kWsBytes = kWsChain + kChainBytes;
+// Where a one launch of the code's smallest levels writes its state and
+// records when they cannot go straight to pinned host memory.
+constexpr size_t kWsOne = kWsChain + kChainBytes;
+constexpr size_t kOneStatsOff = sizeof(bz::OneState);
+constexpr size_t kOneBytes = kOneStatsOff + bz::kOneMaxTasks * sizeof(bz::BatchStat);
+constexpr size_t kWsBytes = kWsOne + ((kOneBytes + 255) & ~(size_t)255);
 static_assert(sizeof(bz::ChainState) <= 128, "bounds fit their line");
 static_assert(kWsRecover + 8 + bz::kHostWords * sizeof(uint64_t) <= kWsIndices, "flag, length and codeword fit");
 static_assert(kWsPreRows - kWsIndices >= (size_t)bz::kBinomT * sizeof(uint32_t),
@@ -105,6 +110,7 @@ uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t 
 // the process ends.
 constexpr size_t kStageBytes = 64 * 1024;
 constexpr size_t kPinnedBytes = kChainBytes + kStageBytes;
+static_assert(kOneBytes <= kChainBytes, "a one launch's state and records fit the read-back buffer");
 class PinnedWords {
   public:
     PinnedWords() {
@@ -124,6 +130,7 @@ class PinnedWords {
         pool().push_back(p_);
     }
     unsigned long long *get() { return p_ ? p_ : fallback_.data(); }
+    bool pinned() const { return p_ != nullptr; }          // device-accessible (hipHostMalloc)
 
   private:
     static std::mutex &mu() { static std::mutex m; return m; }
@@ -436,6 +443,68 @@ bz_status batch_run(bz_code *const *codes, uint32_t count, const bz_opts *o, bz_
     return first;
 }
 
+// The task list of a code's smallest levels (C(k, g) <= kOneLaunchComb, at
+// most kOneMaxTasks tasks and kOneMaxRects rectangles), in Alg. 1's order,
+// with one tiling per (level, lane sums per lane).
+bool build_one_launch(bz_code &c, std::vector<bz::Rect> &rects, std::string &err) {
+    c.one_tasks.clear();
+    c.one_plans.clear();
+    c.one_plan_of.clear();
+    const uint32_t k = c.k, last_j = c.nsets - 1;
+    if (k == c.n) return true;                       // d = 1 without any enumeration
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> plan_index;   // (g, slots) -> index in one_plans
+    for (uint32_t g = 1; g <= k && g <= (uint32_t)bz::kBinomT; ++g) {
+        if ((double)bz::binom_sat(k, g) > bz::kOneLaunchComb) break;
+        if (c.one_tasks.size() + c.nsets > bz::kOneMaxTasks) break;
+        const size_t tasks_before = c.one_tasks.size(), plans_before = c.one_plans.size(),
+                     rects_before = rects.size();
+        std::vector<uint32_t> rect_of_plan;
+        for (uint32_t j = 0; j < c.nsets; ++j) {
+            const uint32_t W = c.W(j), slots = bz::slots_for_w(W);
+            const auto key = std::make_pair(g, slots);
+            if (!plan_index.count(key)) {
+                bz::LevelPlan p;
+                if (!bz::plan_level(k, g, slots, 0, bz::kOneTargetTiles, p, err)) return false;
+                plan_index[key] = (uint32_t)c.one_plans.size();
+                c.one_plans.push_back(std::move(p));
+            }
+            const uint32_t pi = plan_index[key];
+            const bz::LevelPlan &p = c.one_plans[pi];
+            bz::OneTask T{};
+            T.total_tiles = p.total_tiles;
+            T.comb = bz::binom_sat(k, g);
+            T.j = j; T.g = g;
+            T.nrects = (uint32_t)p.rects.size();
+            T.heads_per_tile = p.heads_per_tile;
+            T.W = W;
+            T.row_off = (uint32_t)c.packed_off[j];
+            T.cert_task = certified(j, g, c.num_full, c.partial_rank, k);
+            T.cert_level = certified(last_j, g, c.num_full, c.partial_rank, k);
+            T.last_of_level = j == last_j;
+            c.one_tasks.push_back(T);
+            c.one_plan_of.push_back(pi);
+        }
+        // rectangles of the plans this level added (earlier plans are already placed)
+        for (size_t pi = plans_before; pi < c.one_plans.size(); ++pi)
+            rects.insert(rects.end(), c.one_plans[pi].rects.begin(), c.one_plans[pi].rects.end());
+        if (rects.size() > bz::kOneMaxRects) {
+            // this level's tilings do not fit: it goes to the per-task launches
+            c.one_tasks.resize(tasks_before);
+            c.one_plan_of.resize(tasks_before);
+            for (auto it = plan_index.begin(); it != plan_index.end();)
+                it = it->second >= plans_before ? plan_index.erase(it) : std::next(it);
+            c.one_plans.resize(plans_before);
+            rects.resize(rects_before);
+            break;
+        }
+    }
+    // each task's first rectangle: the plans' rectangles are concatenated in order
+    std::vector<uint32_t> first(c.one_plans.size(), 0);
+    for (size_t pi = 1; pi < c.one_plans.size(); ++pi) first[pi] = first[pi - 1] + (uint32_t)c.one_plans[pi - 1].rects.size();
+    for (size_t t = 0; t < c.one_tasks.size(); ++t) c.one_tasks[t].rect_off = first[c.one_plan_of[t]];
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -497,6 +566,21 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
         *out = c.release();
         return BZ_OK;
     }
+    // the smallest levels' one launch: arguments, task list and tilings after the rows
+    DeviceConst dc;
+    st = device_const(c->device, dc);
+    if (st != BZ_OK) return st;
+    std::vector<bz::Rect> one_rects;
+    {
+        std::string err;
+        if (!build_one_launch(*c, one_rects, err)) return fail(BZ_ELIMIT, err);
+    }
+    size_t one_bytes = 0;
+    if (!c->one_tasks.empty()) {
+        c->dev_one_off = (c->dev_bytes + 255) & ~(size_t)255;
+        one_bytes = 256 + c->one_tasks.size() * sizeof(bz::OneTask) + one_rects.size() * sizeof(bz::Rect);
+        c->dev_bytes = c->dev_one_off + one_bytes;
+    }
     if (hipMalloc(&c->dev, c->dev_bytes) != hipSuccess) return fail(BZ_ENOMEM, "device allocation for Gamma_j");
     // one upload of the whole layout, from pinned memory when it fits (a copy
     // from pageable memory goes through the runtime's staging buffer)
@@ -510,6 +594,33 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
     std::memset(img, 0, pbytes);
     std::memcpy(img, dev_packed.data(), dev_packed.size() * sizeof(uint32_t));
     std::memcpy(img + pbytes, c->full_rows.data(), c->full_rows.size() * sizeof(bz::HostRow));
+    if (one_bytes) {
+        char *o = img + c->dev_one_off;
+        char *dbase = (char *)c->dev + c->dev_one_off;
+        std::memset(o, 0, 256);
+        bz::OneArgs oa{};
+        oa.tasks = (const bz::OneTask *)(dbase + 256);
+        oa.rows = (const uint32_t *)c->dev;
+        oa.full_rows = (const uint64_t *)((const char *)c->dev + c->dev_full_off);
+        oa.rects = (const bz::Rect *)(dbase + 256 + c->one_tasks.size() * sizeof(bz::OneTask));
+        oa.binom = dc.binom;
+        oa.ntasks = (uint32_t)c->one_tasks.size();
+        oa.k = k; oa.k_m = c->partial_rank; oa.m_f = c->num_full;
+        oa.U0 = n - k + 1;
+        oa.row_words = (uint32_t)dev_packed.size();
+        const uint32_t glast = c->one_tasks.back().g;
+        c->one_lds = ((size_t)oa.row_words * 4 + 7) & ~(size_t)7;
+        if (bz::batch_lds_bytes(k, glast) <= 32 * 1024) {
+            oa.lds_g = glast;
+            c->one_lds += bz::batch_lds_bytes(k, glast);
+            c->one_lds_binom = true;
+        }
+        static_assert(sizeof(bz::OneArgs) <= 256, "the one launch's arguments fit their slot");
+        std::memcpy(o, &oa, sizeof(oa));
+        std::memcpy(o + 256, c->one_tasks.data(), c->one_tasks.size() * sizeof(bz::OneTask));
+        std::memcpy(o + 256 + c->one_tasks.size() * sizeof(bz::OneTask), one_rects.data(),
+                    one_rects.size() * sizeof(bz::Rect));
+    }
     if (hipMemcpy(c->dev, img, c->dev_bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(c->dev);
         return fail(BZ_EDEVICE, "upload of Gamma_j");
@@ -580,7 +691,8 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     res->d = 0; res->lower_bound = 0; res->upper_bound = 0; res->last_level = 0;
     res->combinations = 0; res->stats_len = 0; res->launches = 0;
     res->prepare_s = c->prepare_s; res->search_s = 0; res->kernel_s = 0;
-    if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS)) return fail(BZ_EINVAL, "unknown flag");
+    if (opt.flags & ~(uint32_t)(BZ_F_STATS | BZ_F_LEVEL_STOP | BZ_F_NO_WITNESS | BZ_F_TASK_LAUNCHES))
+        return fail(BZ_EINVAL, "unknown flag");
     if (opt.slots_per_lane && opt.slots_per_lane != 2 && opt.slots_per_lane != 4 && opt.slots_per_lane != 8 &&
         opt.slots_per_lane != 16)
         return fail(BZ_EINVAL, "slots_per_lane must be 0, 2, 4, 8 or 16");
@@ -746,8 +858,128 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     uint32_t next_g = 1, next_j = 0;         // the next task in Alg. 1's order
     uint32_t window = 2;
     bool done = false;
+    bool finished_in_one = false;            // the one launch ended the search (witness included)
     std::vector<Task> win;
     std::vector<bz::Rect> staged;
+    // ---- the smallest levels in one work-group (bz_one_kernel)
+    // bz_prepare listed the tasks of the levels of at most kOneLaunchComb sums
+    // and uploaded them with their tilings: one launch of a single work-group
+    // runs them (it goes from task to task itself) and writes a record per task
+    // and its final state straight into pinned host memory; the host replays the
+    // same bookkeeping on the records. A search that is not over by then goes on
+    // with windows of per-task launches below.
+    uint32_t one_run = 0;
+    if (!use_sched && !(opt.flags & BZ_F_TASK_LAUNCHES))
+        for (const bz::OneTask &T : c->one_tasks)
+            if (!opt.max_level || T.g <= opt.max_level) one_run++;
+    if (one_run) {
+        bz::OneRun run{};
+        // pinned read-back memory takes the device's stores directly; the
+        // search that allocates nothing reads back from its scratch instead
+        const bool direct = !na && pinned->pinned();
+        char *out = direct ? (char *)words : ws + kWsOne;
+        run.state = (bz::OneState *)out;
+        run.stats = (bz::BatchStat *)(out + kOneStatsOff);
+        run.cancel = (const uint32_t *)opt.cancel;
+        run.ntasks = one_run;
+        run.level_stop = level_stop;
+        run.want_witness = want_witness;
+        if (ev0) BZ_HIP(hipEventRecord(ev0, st));
+        BZ_HIP(bz::launch_one((const bz::OneArgs *)((const char *)c->dev + c->dev_one_off), run, stats,
+                              c->one_lds_binom, c->one_lds, st));
+        if (ev1) BZ_HIP(hipEventRecord(ev1, st));
+        if (!direct)
+            BZ_HIP(hipMemcpyAsync(words, out, kOneStatsOff + one_run * sizeof(bz::BatchStat), hipMemcpyDeviceToHost,
+                                  st));
+        BZ_HIP(hipStreamSynchronize(st));
+        if (ev0) {
+            float ms = 0.f;
+            BZ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            res->kernel_s += ms * 1e-3;
+        }
+        const auto *sd = (const bz::OneState *)words;
+        const auto *rec = (const bz::BatchStat *)((const char *)words + kOneStatsOff);
+        const uint32_t nrun = sd->ntasks;
+        if (nrun > one_run) return fail(BZ_EDEVICE, "internal: one launch ran more tasks than listed");
+        // Alg. 1's bookkeeping replayed on the records (the host is the authority)
+        bool stop = false;
+        int64_t best_i = -1;                                       // the winning task, if in this launch
+        for (uint32_t i = 0; i < nrun && !stop; ++i) {
+            const bz::OneTask &T = c->one_tasks[i];
+            const bz::BatchStat &r = rec[i];
+            if (r.matrix != T.j || r.level != T.g) return fail(BZ_EDEVICE, "internal: one launch's record order");
+            const uint32_t j = T.j, g = T.g, tmin = r.min_weight;
+            res->last_level = g;
+            res->launches++;
+            res->combinations += r.combinations;
+            if (res->stats && res->stats_len < res->stats_cap) {
+                bz_level_stat &s = res->stats[res->stats_len];
+                s.matrix = (uint16_t)j; s.level = (uint16_t)g; s.min_weight = tmin;
+                s.count_at_min = r.count_at_min;
+                s.combinations = r.combinations;
+            }
+            res->stats_len++;
+            if (tmin < U || (tmin == U && !best.have)) {
+                U = tmin;
+                best.have = true;
+                best_i = i;
+            }
+            next_j = j == last_j ? 0 : j + 1;
+            next_g = j == last_j ? g + 1 : g;
+            if (r.combinations != T.comb) {
+                if (U > Lcert) return fail(BZ_EDEVICE, "internal: task ended early without a certificate");
+                L = std::max(L, Lcert);
+                stop = true;
+                break;
+            }
+            Lcert = std::max(Lcert, T.cert_task);
+            if (!level_stop) {
+                L = std::max(L, Lcert);
+                if (L >= U) stop = true;
+            }
+            if (!stop && T.last_of_level) {
+                L = std::max(L, T.cert_level);
+                if (L >= U || g == k) stop = true;
+            }
+        }
+        if (best_i >= 0) {
+            // the winning tile as the device recorded it, and its rectangle
+            if ((uint32_t)best_i != sd->best_task) return fail(BZ_EDEVICE, "internal: one launch's winning task");
+            const bz::OneTask &T = c->one_tasks[best_i];
+            const bz::LevelPlan &p = c->one_plans[c->one_plan_of[best_i]];
+            best.j = T.j; best.g = T.g; best.tile = sd->best_tile;
+            best.slots = bz::slots_for_w(T.W);
+            best.ht = p.heads_per_tile;
+            best.pre.clear();
+            size_t lo = 0, hi = p.rects.size() - 1;
+            while (lo < hi) {
+                size_t mid = (lo + hi + 1) / 2;
+                if (p.rects[mid].tile_begin <= best.tile) lo = mid; else hi = mid - 1;
+            }
+            best.rect = p.rects[lo];
+        }
+        const uint32_t dev_status = sd->status;
+        if (dev_status == bz::kOneCanceled || dev_status == bz::kOneRunning) {
+            // the work-group left before its end: only the cancel word does that
+            if (dev_status == bz::kOneRunning || !(opt.cancel && *opt.cancel))
+                return fail(BZ_EDEVICE, "internal: one launch left early");
+            status = BZ_ECANCELED;
+            g_err = "canceled";
+            done = true;
+        } else {
+            const bool dev_stop = dev_status == bz::kOneStopped;
+            if (dev_stop != stop || sd->U != U || sd->L != L || sd->Lcert != Lcert)
+                return fail(BZ_EDEVICE, "internal: device and host bookkeeping disagree (one launch)");
+            if (stop) {
+                done = true;
+                finished_in_one = true;
+                if (want_witness) {
+                    if (sd->wit_flag != 1) return fail(BZ_EDEVICE, "internal: witness not found in its tile");
+                    for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = sd->witness[w];
+                }
+            }
+        }
+    }
     while (!done) {
         if (next_j == 0) {
             if (next_g > k || L >= U) break;
@@ -967,7 +1199,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         status = BZ_ELIMIT;
         g_err = "stats buffer too small";
     }
-    if (status == BZ_OK && want_witness) {
+    if (status == BZ_OK && want_witness && !finished_in_one) {
         if (!best.have) return fail(BZ_EDEVICE, "internal: no witness tile");
         bz::RecoverArgs ra{};
         const uint32_t j = best.j;

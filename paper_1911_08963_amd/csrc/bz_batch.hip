@@ -317,6 +317,259 @@ __device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, u
     return t;
 }
 
+// ---- one code's smallest levels in one work-group
+//
+// The single-code search hands its first levels, while their tasks are tiny,
+// to one launch of bz_one_kernel: a single work-group, whose four waves are
+// always resident together, runs the tasks (Gamma_j, g) in Alg. 1's order
+// (OneTask list, fixed by the host). Each task's tiles are dealt to the waves
+// round-robin; every wave keeps its key, combination count and statistics word
+// in LDS; after a barrier wave 0 merges them and applies Alg. 1's bookkeeping
+// (the step kernel's rules), and after a second barrier the waves go on with
+// the next task or leave. When the search is over wave 0 finds the witness in
+// the winning tile. Nothing but LDS and the final records is written, and no
+// device-scope atomic is needed. Larger levels go on as one launch per task.
+
+template <bool STATS>
+__device__ __forceinline__ void one_tile(const OneArgs &a, const OneTask &T, uint64_t tile, uint32_t lane,
+                                         cptr64 binom_c, const uint64_t *sb, uint32_t bt, const uint32_t *lrows,
+                                         uint32_t u_prev, uint32_t exit_at, unsigned long long *words) {
+    const bool partial = T.j >= a.m_f;
+    const uint32_t *rows = (const uint32_t *)uni64((uint64_t)(a.rows + T.row_off));
+    TaskArgs t{};
+    t.rows = rows;
+    t.binom = a.binom;
+    t.rects = a.rects + T.rect_off;
+    t.key = words;
+    t.ncomb = words + 1;
+    t.stats = words + 2;
+    t.nrects = T.nrects;
+    t.k = a.k;
+    t.k_low = partial ? a.k_m : a.k;
+    t.g = T.g;
+    t.heads_per_tile = T.heads_per_tile;
+    t.total_tiles = T.total_tiles;
+    t.u_prev = u_prev;
+    t.exit_at = exit_at;
+    cptr32 rc = (cptr32)rows;
+    cptr_rect rp = (cptr_rect)t.rects;
+    const uint32_t *srow = lrows + T.row_off;
+    switch (T.W * 2 + (partial ? 1u : 0u)) {
+#define BZ_CASE(WW)                                                                                   \
+    case WW * 2:                                                                                      \
+        run_tile<WW, slots_for_w(WW), false, STATS>(t, rc, binom_c, srow, sb, bt, rp, tile, lane);    \
+        break;                                                                                        \
+    case WW * 2 + 1:                                                                                  \
+        run_tile<WW, slots_for_w(WW), true, STATS>(t, rc, binom_c, srow, sb, bt, rp, tile, lane);     \
+        break;
+        BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
+#undef BZ_CASE
+    default: break;
+    }
+}
+
+// The witness of a finished search: a combination of weight U in the winning
+// tile (one wave), then the XOR of its full rows.
+__device__ bool one_witness(const OneArgs &a, const OneTask &T, uint64_t tile, uint32_t U, uint32_t lane,
+                            cptr64 binom_c, const uint64_t *sb, uint32_t bt, const uint32_t *lrows,
+                            uint64_t (&cw)[kHostWords]) {
+    const bool partial = T.j >= a.m_f;
+    const uint32_t *rows = (const uint32_t *)uni64((uint64_t)(a.rows + T.row_off));
+    TaskArgs t{};
+    t.rows = rows;
+    t.rects = a.rects + T.rect_off;
+    t.nrects = T.nrects;
+    t.k = a.k;
+    t.k_low = partial ? a.k_m : a.k;
+    t.g = T.g;
+    t.heads_per_tile = T.heads_per_tile;
+    cptr32 rc = (cptr32)rows;
+    cptr_rect rp = (cptr_rect)t.rects;
+    const uint32_t *srow = lrows + T.row_off;
+    TileGeom g{};
+    uint64_t q = 0, h = 0;
+    bool found = false;
+    switch (T.W) {
+#define BZ_FIND(WW)                                                                                          \
+    case WW:                                                                                                 \
+        found = find_in_tile<WW, slots_for_w(WW)>(t, rc, binom_c, srow, sb, bt, rp, tile, lane, U, g, q, h); \
+        break;
+        BZ_FIND(1) BZ_FIND(2) BZ_FIND(3) BZ_FIND(4) BZ_FIND(5) BZ_FIND(6) BZ_FIND(7) BZ_FIND(8)
+#undef BZ_FIND
+    default: break;
+    }
+    if (!found) return false;
+    const uint64_t *full = a.full_rows + (size_t)T.j * a.k * kHostWords;
+    unrank_xor(a.binom, q, g.lane_t, g.lane_off, g.lane_n, full, cw);
+    if (g.head_t) unrank_xor(a.binom, h, g.head_t, g.head_off, g.head_n, full, cw);
+    return true;
+}
+
+// Task t's fields, known to be uniform (readfirstlane): the loops they bound
+// are then left by the whole wave at once.
+__device__ __forceinline__ OneTask one_task(const OneTask *p) {
+    OneTask T;
+    T.total_tiles = uni64(p->total_tiles);
+    T.comb = uni64(p->comb);
+    T.j = uni(p->j); T.g = uni(p->g); T.rect_off = uni(p->rect_off); T.nrects = uni(p->nrects);
+    T.heads_per_tile = uni(p->heads_per_tile); T.W = uni(p->W); T.row_off = uni(p->row_off);
+    T.cert_task = uni(p->cert_task); T.cert_level = uni(p->cert_level); T.last_of_level = uni(p->last_of_level);
+    T._pad[0] = T._pad[1] = 0;
+    return T;
+}
+
+// Launched as a single work-group of kBlock threads. The arguments live in
+// device memory (a by-value struct whose address the device functions take
+// would be copied to per-lane scratch, and its fields would no longer be known
+// to be uniform).
+template <bool STATS, bool LDS_BINOM>
+__global__ __launch_bounds__(kBlock) void bz_one_kernel(const OneArgs *__restrict__ ap, OneRun run) {
+    const OneArgs &a = *ap;
+    constexpr uint32_t kWaves = kBlock / kWaveSize;
+    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
+    const uint32_t wv = uni(threadIdx.x / kWaveSize);
+    extern __shared__ uint64_t one_lds[];
+    uint32_t *lrows = (uint32_t *)one_lds;
+    for (uint32_t i = threadIdx.x; i < a.row_words; i += blockDim.x) lrows[i] = a.rows[i];
+    const uint64_t *sb = a.binom;
+    uint32_t bt = kBinomT + 1;
+    if (LDS_BINOM) {
+        uint64_t *lb = one_lds + (a.row_words + 1) / 2;
+        bt = a.lds_g + 1;
+        for (uint32_t i = threadIdx.x; i < (a.k + 1) * bt; i += blockDim.x) {
+            const uint32_t x = i / bt, y = i - x * bt;
+            lb[i] = a.binom[x * (kBinomT + 1) + y];
+        }
+        sb = lb;
+    }
+    cptr64 binom_c = (cptr64)a.binom;
+    // per wave: key, combinations, statistics word of the current task
+    __shared__ unsigned long long words[kWaves][3];
+    // the bounds, written by wave 0 between the barriers: U, exit_at, go on (1) or leave (0)
+    __shared__ uint32_t shared_bounds[3];
+    OneState *S = run.state;
+    uint32_t U = a.U0, L = 1, Lcert = 1, have_best = 0, best_task = 0;
+    uint64_t best_tile = 0, combos = 0;
+    uint32_t status = kOneRunning, ntasks = 0;
+    if (threadIdx.x == 0) {
+        shared_bounds[0] = U;
+        shared_bounds[1] = STATS ? 0u : Lcert;
+        shared_bounds[2] = 1;
+    }
+    for (uint32_t t = 0; t < run.ntasks; ++t) {
+        // wave 0 has read every wave's words of the previous task before this barrier
+        __syncthreads();
+        if (!uni(shared_bounds[2])) break;              // the search stopped (uniform for the group)
+        if (lane == 0) {
+            words[wv][0] = ~0ull;
+            words[wv][1] = 0;
+            words[wv][2] = ~0ull;
+        }
+        const OneTask T = one_task(a.tasks + t);
+        const uint32_t u_prev = uni(shared_bounds[0]), exit_at = uni(shared_bounds[1]);
+        bool canceled = false;
+        if (run.cancel) canceled = uni(__hip_atomic_load(run.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0;
+        if (!canceled) {
+            for (uint64_t tile = wv; tile < T.total_tiles; tile += kWaves) {
+                if (exit_at) {
+                    const uint32_t cur = min((uint32_t)(words[wv][0] >> kTileBits), u_prev);
+                    if (uni(cur) <= exit_at) break;     // the bound is met
+                }
+                one_tile<STATS>(a, T, tile, lane, binom_c, sb, bt, lrows, u_prev, exit_at, words[wv]);
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            // merge the waves' words, then Alg. 1's bookkeeping for task t
+            unsigned long long key = ~0ull, nc = 0;
+            uint32_t smin = 0xffffffffu;
+            uint64_t scnt = 0;
+            for (uint32_t w = 0; w < kWaves; ++w) {
+                key = key < words[w][0] ? key : words[w][0];
+                nc += words[w][1];
+                if (STATS && words[w][2] != ~0ull) {
+                    const uint32_t m = (uint32_t)(words[w][2] >> kCountBits);
+                    const uint64_t c = words[w][2] & kCountMask;
+                    if (m < smin) { smin = m; scnt = c; } else if (m == smin) scnt += c;
+                }
+            }
+            const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
+            if (canceled) {
+                // the task did not run: no record, leave
+                status = kOneCanceled;
+                if (lane == 0) shared_bounds[2] = 0;
+                continue;
+            }
+            ntasks = t + 1;
+            combos += nc;
+            if (lane == 0) {
+                BatchStat st;
+                st.matrix = (uint16_t)T.j;
+                st.level = (uint16_t)T.g;
+                st.min_weight = tmin;
+                st.count_at_min = STATS ? scnt : 0ull;
+                st.combinations = nc;
+                run.stats[t] = st;
+            }
+            if (tmin < U || (tmin == U && !have_best)) {
+                U = tmin;
+                have_best = 1; best_task = t; best_tile = key & kTileMask;
+            }
+            if (nc != T.comb) {
+                // waves skip tiles only once U <= the bound certified before this task
+                L = max(L, Lcert);
+                status = kOneStopped;
+            } else {
+                Lcert = max(Lcert, T.cert_task);
+                if (!run.level_stop) {
+                    L = max(L, Lcert);
+                    if (L >= U) status = kOneStopped;
+                }
+                if (status == kOneRunning && T.last_of_level) {
+                    L = max(L, T.cert_level);
+                    if (L >= U || T.g == a.k) status = kOneStopped;   // g == k: every combination enumerated
+                }
+                if (status == kOneRunning && t + 1 >= run.ntasks) status = kOneContinue;
+            }
+            if (lane == 0) {
+                shared_bounds[0] = U;
+                shared_bounds[1] = STATS ? 0u : Lcert;
+                shared_bounds[2] = status == kOneRunning ? 1u : 0u;
+            }
+        }
+    }
+    if (wv == 0) {
+        uint32_t wit = 0;
+        if (status == kOneStopped && run.want_witness && have_best) {
+            uint64_t cw[kHostWords] = {0, 0, 0, 0};
+            const bool ok = one_witness(a, one_task(a.tasks + best_task), best_tile, U, lane, binom_c, sb, bt,
+                                        lrows, cw);
+            wit = ok ? 1u : 2u;
+            if (lane == 0)
+                for (int w = 0; w < kHostWords; ++w) S->witness[w] = cw[w];
+        }
+        if (lane == 0) {
+            S->wit_flag = wit;
+            S->U = U; S->L = L; S->Lcert = Lcert; S->status = status; S->ntasks = ntasks;
+            S->have_best = have_best; S->best_task = best_task; S->best_tile = best_tile;
+            S->combinations = combos;
+        }
+    }
+}
+
+hipError_t launch_one(const OneArgs *args, const OneRun &run, bool stats, bool lds_binom, size_t lds,
+                      hipStream_t st) {
+    if (stats && lds_binom)
+        hipLaunchKernelGGL((bz_one_kernel<true, true>), dim3(1), dim3(kBlock), lds, st, args, run);
+    else if (stats)
+        hipLaunchKernelGGL((bz_one_kernel<true, false>), dim3(1), dim3(kBlock), lds, st, args, run);
+    else if (lds_binom)
+        hipLaunchKernelGGL((bz_one_kernel<false, true>), dim3(1), dim3(kBlock), lds, st, args, run);
+    else
+        hipLaunchKernelGGL((bz_one_kernel<false, false>), dim3(1), dim3(kBlock), lds, st, args, run);
+    return hipGetLastError();
+}
+
 // ---- serving
 
 __device__ __forceinline__ uint64_t sys_load64(const void *p) {

@@ -75,6 +75,29 @@ struct LevelPlan {
 
 bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                 uint64_t target_tiles, LevelPlan &out, std::string &err);
+
+// A code's smallest levels run in one launch of a single work-group
+// (bz_one_kernel): the levels of at most kOneLaunchComb sums, tasks small
+// enough that one compute unit finishes them sooner than a launch of their own
+// would start. Their task list and tilings are fixed by the code, so
+// bz_prepare builds and uploads them with Gamma_j.
+constexpr double kOneLaunchComb = 4096.0;
+constexpr uint64_t kOneTargetTiles = 8;            // tiles per task: two per wave of the work-group
+constexpr uint32_t kOneMaxTasks = 128;
+constexpr uint32_t kOneMaxRects = 64;
+
+// Task (Gamma_j, g) of that launch, in Alg. 1's order.
+struct OneTask {
+    uint64_t total_tiles;         // tiles of the task's tiling
+    uint64_t comb;                // C(k, g): what a complete task enumerates
+    uint32_t j, g, rect_off, nrects;
+    uint32_t heads_per_tile, W, row_off;   // row width of Gamma_j; dword offset of its packed rows
+    uint32_t cert_task;           // bound certified once this task is complete
+    uint32_t cert_level;          // Alg. 1's L once the level is complete
+    uint32_t last_of_level;       // the level's last matrix
+    uint32_t _pad[2];
+};
+static_assert(sizeof(OneTask) == 64, "OneTask is 64 bytes");
 // The same for the g-subsets of rows [lo, lo + n) (plan_level is lo = 0, n = k).
 bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
                 uint64_t target_tiles, LevelPlan &out, std::string &err);
@@ -97,6 +120,14 @@ struct bz_code {
     void *dev = nullptr;                // device copy: packed rows, then full rows
     size_t dev_bytes = 0;
     size_t dev_full_off = 0;            // byte offset of the full rows in dev
+    // the smallest levels' one launch: task list, the tiling of each task's
+    // level (one_plan_of), and where its arguments, tasks and rectangles sit in dev
+    std::vector<bz::OneTask> one_tasks;
+    std::vector<bz::LevelPlan> one_plans;
+    std::vector<uint32_t> one_plan_of;
+    size_t dev_one_off = 0;
+    size_t one_lds = 0;                 // LDS bytes of the launch
+    bool one_lds_binom = false;         // binomials staged in LDS
     double prepare_s = 0.0;
     uint32_t W(uint32_t j) const { return j < num_full ? W_full : W_partial; }
     uint32_t k_low(uint32_t j) const { return j < num_full ? k : partial_rank; }

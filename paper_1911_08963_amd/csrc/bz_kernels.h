@@ -169,6 +169,53 @@ struct BatchArgs {
     uint32_t lds_k, lds_g, _pad;
 };
 
+// ---- one code's smallest levels in one work-group (bz_min_distance)
+//
+// bz_prepare lists the tasks (Gamma_j, g) of the code's smallest levels in
+// Alg. 1's order (OneTask) and uploads them with their tilings and the launch's
+// arguments; a search launches one work-group over them and gets a record per
+// task and the final state.
+
+// Status of a launch (OneState::status).
+enum : uint32_t { kOneRunning = 0, kOneStopped = 1, kOneContinue = 2, kOneCanceled = 3 };
+
+// The result, written by the work-group.
+struct alignas(128) OneState {
+    uint32_t U, L, Lcert, status;
+    uint32_t ntasks, have_best, best_task, wit_flag;   // tasks run; witness: 0 not sought, 1 found, 2 not found
+    uint64_t best_tile, combinations;
+    uint64_t witness[kHostWords];
+};
+static_assert(sizeof(OneState) == 128, "OneState is one 128-byte line");
+
+// Arguments fixed by the code (built by bz_prepare, in device memory).
+struct OneArgs {
+    const OneTask *tasks;
+    const uint32_t *rows;         // packed rows of every Gamma_j ((k + 1) x W per matrix)
+    const uint64_t *full_rows;    // full rows (witness), k x kHostWords per matrix
+    const Rect *rects;
+    const uint64_t *binom;        // kBinomRows x (kBinomT + 1)
+    uint32_t ntasks, k, k_m, m_f;
+    uint32_t U0;                  // n - k + 1
+    uint32_t lds_g;               // binomials C(x, y), y <= lds_g, staged in LDS (0: read from binom)
+    uint32_t row_words;           // packed-row dwords of all matrices, staged in LDS
+    uint32_t _pad;
+};
+
+// Arguments of one search (by value).
+struct OneRun {
+    OneState *state;              // the result: host-visible pinned memory, or device memory
+    BatchStat *stats;             // one record per task run
+    const uint32_t *cancel;       // host-visible cancel word, or null
+    uint32_t ntasks;              // run the first ntasks tasks of the list
+    uint32_t level_stop, want_witness, _pad;
+};
+
+// One work-group of kBlock threads. args: in device memory. lds: the packed
+// rows, then the binomial table (batch_lds_bytes(k, lds_g)) when lds_binom.
+hipError_t launch_one(const OneArgs *args, const OneRun &run, bool stats, bool lds_binom, size_t lds,
+                      hipStream_t st);
+
 // ---- serving: a resident search that admits codes while it runs
 //
 // The host stages each request in pinned host memory and publishes it by

@@ -12,9 +12,12 @@ lane-0 branch through the loop.
 
 This compiles the kernels to gfx950 assembly with hipcc, rebuilds each loop
 from the compiler's loop annotations, and checks that no loop containing a
-v_readfirstlane is closed by an exec-tested branch (s_cbranch_execnz or
-s_cbranch_execz back to its header). A small kernel with exactly that shape,
-compiled the same way, checks that the analysis finds it.
+v_readfirstlane is closed by the back edge of a loop that lanes leave one at a
+time: an s_cbranch_execnz to its header (the latch has removed the lanes that
+left). (An s_cbranch_execz to the header is the compiler's "no lane active,
+fall through" shortcut after branch relaxation, not a back edge lanes take
+separately.) A small kernel with exactly the hazardous shape, compiled the same
+way, checks that the analysis finds it.
 """
 from __future__ import annotations
 
@@ -56,8 +59,8 @@ def _compile(src_path, out_path):
 
 
 def divergent_loops_with_broadcast(asm: str, kernel_pattern: str):
-    """(kernel, loop header) of every loop that holds a v_readfirstlane and whose
-    back edge to the header is an exec-tested branch."""
+    """(kernel, loop header) of every loop that holds a v_readfirstlane and is
+    closed by an s_cbranch_execnz back to its header."""
     found = []
     kernels = re.findall(kernel_pattern, asm, re.M)
     for k in kernels:
@@ -100,7 +103,7 @@ def divergent_loops_with_broadcast(asm: str, kernel_pattern: str):
             body = [lines[j] for b in bl for j in range(b[1], b[2] + 1)]
             if not any("v_readfirstlane" in x and not x.strip().startswith(";") for x in body):
                 continue
-            back = re.compile(r"\s*s_cbranch_exec(?:nz|z)\s+" + re.escape(h) + r"\b")
+            back = re.compile(r"\s*s_cbranch_execnz\s+" + re.escape(h) + r"\b")
             if any(back.match(x) for x in body):
                 found.append((k, h))
     return kernels, found
@@ -130,3 +133,14 @@ def test_schedule_kernels_broadcast_in_uniform_loops(tmp_path):
     kernels, found = divergent_loops_with_broadcast(asm, r"^(_ZN2bz\d+bz_sched_kernel\w*):")
     assert len(kernels) == 32
     assert not found, found[:4]
+
+
+@needs_hipcc
+def test_batch_and_one_launch_kernels_broadcast_in_uniform_loops(tmp_path):
+    """The batched kernel and the one-launch single-code kernel: their persistent loops read
+    the cursor and the claim results through readfirstlane and must be left by the whole wave."""
+    asm = _compile(os.path.join(CSRC, "bz_batch.hip"), tmp_path / "bz_batch.s")
+    for pattern, count in ((r"^(_ZN2bz\d+bz_batch_kernel\w*):", 4), (r"^(_ZN2bz\d+bz_one_kernel\w*):", 4)):
+        kernels, found = divergent_loops_with_broadcast(asm, pattern)
+        assert len(kernels) == count
+        assert not found, found[:4]
