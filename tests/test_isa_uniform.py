@@ -119,27 +119,24 @@ def test_analysis_finds_a_divergent_loop(tmp_path):
     assert found, "the probe's lane-dependent loop around a readfirstlane was not found"
 
 
-@needs_hipcc
-def test_enumeration_kernels_broadcast_in_uniform_loops(tmp_path):
-    asm = _compile(os.path.join(CSRC, "bz_kernels.hip"), tmp_path / "bz_kernels.s")
+def test_enumeration_kernels_broadcast_in_uniform_loops(isa_asm):
+    asm = isa_asm["bz_kernels.hip"]
     kernels, found = divergent_loops_with_broadcast(asm, r"^(_ZN2bz\d+bz_\w+_kernel\w*):")
     assert sum("bz_enum_kernel" in k for k in kernels) >= 64
     assert not found, found[:4]
 
 
-@needs_hipcc
-def test_schedule_kernels_broadcast_in_uniform_loops(tmp_path):
-    asm = _compile(os.path.join(CSRC, "bz_sched.hip"), tmp_path / "bz_sched.s")
+def test_schedule_kernels_broadcast_in_uniform_loops(isa_asm):
+    asm = isa_asm["bz_sched.hip"]
     kernels, found = divergent_loops_with_broadcast(asm, r"^(_ZN2bz\d+bz_sched_kernel\w*):")
     assert len(kernels) == 32
     assert not found, found[:4]
 
 
-@needs_hipcc
-def test_batch_and_one_launch_kernels_broadcast_in_uniform_loops(tmp_path):
-    """The batched kernel and the one-launch single-code kernel: their persistent loops read
-    the cursor and the claim results through readfirstlane and must be left by the whole wave."""
-    asm = _compile(os.path.join(CSRC, "bz_batch.hip"), tmp_path / "bz_batch.s")
+def test_batch_and_one_launch_kernels_broadcast_in_uniform_loops(isa_asm):
+    """The batched kernel and the one-launch single-code kernel: their loops read the claim
+    results and the task fields through readfirstlane and must be left by the whole wave."""
+    asm = isa_asm["bz_batch.hip"]
     for pattern, count in ((r"^(_ZN2bz\d+bz_batch_kernel\w*):", 4), (r"^(_ZN2bz\d+bz_one_kernel\w*):", 4)):
         kernels, found = divergent_loops_with_broadcast(asm, pattern)
         assert len(kernels) == count
