@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void bz_collect_kernel(CollectArgs a) {
                 if (idx < a.cap) {
                     CollectHit &o = a.hits[idx];
                     o.tile = tile;
-                    o.q = base + (uint64_t)s * kWaveSize + lane;
+                    o.q = base + (uint64_t)lane * SLOTS + s;
                     o.h = h0 + step;
                 }
             }

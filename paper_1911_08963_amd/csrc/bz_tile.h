@@ -171,17 +171,45 @@ __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_
     return t;
 }
 
-// The lane subsets of a tile: lane l, slot s holds lane subset
-// lb * 64 * SLOTS + s * 64 + l (colex rank); P[s] is the XOR of its rows, low[s]
-// the number of its rows below k_low, pen[s] = 0x10000 when the rank is past
-// the factor's end. Returns the number of valid lane subsets (uniform).
-// No branch depends on the lane: a lane past the end unranks rank 0 and is
-// masked by pen; only a slot with no valid lane at all is skipped, a uniform
-// test. (With an "if (valid)" per lane here the optimizer specialised the
-// tile's uniform combination count per divergent path and the wave took the
-// wrong path's value.)
+// The lane subsets of a tile: lane l, slot s holds the lane subset of colex
+// rank lb * 64 * SLOTS + l * SLOTS + s, so that a lane's slots are consecutive
+// ranks. P[s] is the XOR of its rows, low[s] the number of its rows below
+// k_low, pen[s] = 0x10000 when the rank is past the factor's end. Returns the
+// number of valid lane subsets (uniform).
+// A lane unranks its first subset (colex digits, binomials from sbin) and
+// reaches the next ones by colex successor steps on a 64-bit mask of the lane
+// range (Gosper's step), XORing only the rows that change, about two per step.
+// A lane range wider than 64 rows unranks every slot instead.
+// No branch depends on the lane except the loop over a step's changed rows: a
+// lane past the end unranks rank 0 and is masked by pen. (With an "if (valid)"
+// per lane around the unranking the optimizer once specialised the tile's
+// uniform combination count per divergent path and the wave took the wrong
+// path's value.)
 // pre / pre_low: the XOR and the count below k_low of rows joined to every
 // combination of the tile (a prefix task's prefix; zero otherwise).
+// Unranks colex rank r of the lane range (lane_n <= 64) into P (XOR of its rows)
+// and returns its rows as a mask of the range.
+template <int W>
+__device__ __forceinline__ uint64_t unrank_lane(const TileGeom &t, uint64_t r, const uint32_t *srow,
+                                                const uint64_t *sbin, uint32_t bt, float lf_top,
+                                                uint32_t (&P)[W]) {
+    uint64_t x = 0;
+    uint32_t hi = t.lane_n - 1;
+    float lf = lf_top;
+    for (uint32_t i = t.lane_t; i >= 1; --i) {
+        uint64_t bc;
+        const uint32_t c = colex_digit_est(sbin, bt, i, hi, r, lf, bc);
+        r -= bc;
+        const uint32_t row = t.lane_off + c;
+#pragma unroll
+        for (int w = 0; w < W; ++w) P[w] ^= srow[row * W + w];
+        x |= 1ull << c;                            // c < lane_n <= 64
+        lf -= __builtin_amdgcn_logf((float)i);
+        hi = c - 1;
+    }
+    return x;
+}
+
 template <int W, int SLOTS>
 __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low, const uint32_t *srow,
                                                const uint64_t *sbin, uint32_t bt, uint32_t lane,
@@ -193,29 +221,67 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
         uni(t.lane_count > base ? (uint32_t)umin64(t.lane_count - base, (uint64_t)kWaveSize * SLOTS) : 0u);
     float lf_top = 0.f;                            // log2(lane_t!)
     for (uint32_t j = 2; j <= t.lane_t; ++j) lf_top += __builtin_amdgcn_logf((float)j);
+    const uint64_t q0 = base + (uint64_t)lane * SLOTS;
+    // rows of the lane range below k_low, as a mask of the range
+    uint64_t low_mask = 0;
+    if (k_low > t.lane_off) {
+        const uint32_t nl = k_low - t.lane_off;
+        low_mask = nl >= 64 ? ~0ull : ((1ull << nl) - 1);
+    }
+    if (t.lane_n <= 64) {
+        uint32_t cur[W];
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const uint64_t first = base + (uint64_t)s * kWaveSize;
-        const uint64_t q = first + lane;
-        const bool valid = q < t.lane_count;
+        for (int w = 0; w < W; ++w) cur[w] = pre[w];
+        uint64_t x = unrank_lane<W>(t, q0 < t.lane_count ? q0 : 0ull, srow, sbin, bt, lf_top, cur);
+        const uint64_t range = t.lane_n >= 64 ? ~0ull : ((1ull << t.lane_n) - 1);
 #pragma unroll
-        for (int w = 0; w < W; ++w) P[s][w] = pre[w];
-        low[s] = pre_low;
-        pen[s] = valid ? 0u : 0x10000u;
-        if (first >= t.lane_count) continue;      // uniform: a slot with no valid lane
-        uint64_t r = valid ? q : 0ull;
-        uint32_t hi = t.lane_n - 1;
-        float lf = lf_top;
-        for (uint32_t i = t.lane_t; i >= 1; --i) {
-            uint64_t bc;
-            const uint32_t c = colex_digit_est(sbin, bt, i, hi, r, lf, bc);
-            r -= bc;
-            const uint32_t row = t.lane_off + c;
+        for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
-            low[s] += (row < k_low) ? 1u : 0u;
-            lf -= __builtin_amdgcn_logf((float)i);
-            hi = c - 1;
+            for (int w = 0; w < W; ++w) P[s][w] = cur[w];
+            low[s] = pre_low + (uint32_t)__builtin_popcountll(x & low_mask);
+            pen[s] = (q0 + (uint64_t)s < t.lane_count) ? 0u : 0x10000u;
+            if (s + 1 < SLOTS) {
+                // colex successor: the lowest run of ones moves up by one, the rest of it drops to the bottom
+                const uint64_t u = x & (~x + 1);
+                const uint64_t v = x + u;
+                const uint64_t nx = v | (((v ^ x) >> 2) >> __builtin_ctzll(x | (1ull << 63)));
+                // past the last subset of the range the slots are masked: keep the sum
+                const bool ok = v != 0 && (nx & ~range) == 0;
+                uint64_t diff = ok ? (x ^ nx) : 0ull;
+                while (diff) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(diff);
+                    diff &= diff - 1;
+                    const uint32_t row = t.lane_off + b;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) cur[w] ^= srow[row * W + w];
+                }
+                x = ok ? nx : x;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const uint64_t q = q0 + (uint64_t)s;
+            const bool valid = q < t.lane_count;
+#pragma unroll
+            for (int w = 0; w < W; ++w) P[s][w] = pre[w];
+            pen[s] = valid ? 0u : 0x10000u;
+            low[s] = pre_low;
+            if (base + (uint64_t)s >= t.lane_count) continue;      // uniform: a slot with no valid lane
+            uint64_t r = valid ? q : 0ull;
+            uint32_t hi = t.lane_n - 1;
+            float lf = lf_top;
+            for (uint32_t i = t.lane_t; i >= 1; --i) {
+                uint64_t bc;
+                const uint32_t c = colex_digit_est(sbin, bt, i, hi, r, lf, bc);
+                r -= bc;
+                const uint32_t row = t.lane_off + c;
+#pragma unroll
+                for (int w = 0; w < W; ++w) P[s][w] ^= srow[row * W + w];
+                low[s] += (row < k_low) ? 1u : 0u;
+                lf -= __builtin_amdgcn_logf((float)i);
+                hi = c - 1;
+            }
         }
     }
     return nvalid;
@@ -427,7 +493,7 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
 
 // Finds one combination of the tile whose weight is target (the tile is
 // known to hold one). The lane subsets are taken one slot at a time (slot s:
-// ranks lb * 64 * SLOTS + s * 64 + lane), each against a walk over the tile's
+// ranks lb * 64 * SLOTS + lane * SLOTS + s), each against a walk over the tile's
 // heads; after each head step a ballot tells whether any lane hit. Returns
 // (uniform) true and, in every lane, the lane-subset rank and head rank of the
 // first hit. Few registers: this runs inside the resident serving kernel.
@@ -441,9 +507,9 @@ __device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cpt
     const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
     bool found = false;
     for (int s = 0; s < SLOTS && !found; ++s) {
-        const uint64_t base = t.lb * (kWaveSize * SLOTS) + (uint64_t)s * kWaveSize;
-        if (base >= t.lane_count) break;
-        const uint64_t q = base + lane;
+        const uint64_t base = t.lb * (kWaveSize * SLOTS) + (uint64_t)s;
+        if (base >= t.lane_count) break;                // lane 0 past the end: every lane is
+        const uint64_t q = base + (uint64_t)lane * SLOTS;
         const bool valid = q < t.lane_count;      // no lane-dependent branch (see lane_setup)
         uint32_t P[W], low = 0;
         const uint32_t pen = valid ? 0u : 0x10000u;
@@ -469,7 +535,7 @@ __device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cpt
             for (int w = 0; w < W; ++w) v += __builtin_popcount(H[w] ^ P[w]);
             const uint64_t ballot = __builtin_amdgcn_ballot_w64(v == target);
             if (ballot == 0) return false;
-            q_hit = base + (uint64_t)__builtin_ctzll(ballot);
+            q_hit = base + (uint64_t)__builtin_ctzll(ballot) * SLOTS;
             h_hit = h0 + step;
             found = true;
             return true;
