@@ -33,7 +33,9 @@ bz_status bz_debug_prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint3
  * [lane_off, lane_off + lane_n) and a head_t-subset of [head_off, head_off + head_n). */
 typedef struct {
     uint32_t lane_off, lane_n, lane_t, head_off;
-    uint32_t head_n, head_t, _reserved0, _reserved1;
+    uint32_t head_n, head_t;
+    uint32_t lane_mult;                /* blocks of 64 * slots lane subsets per tile */
+    uint32_t _reserved1;
     uint64_t lane_count, head_count;   /* C(lane_n, lane_t), C(head_n, head_t)   */
     uint64_t tile_begin;               /* first tile of this rectangle           */
     uint64_t lane_blocks, head_blocks; /* tiles along each factor               */
@@ -41,9 +43,11 @@ typedef struct {
 } bz_debug_rect;
 
 /* The tiling the search uses for level g of a Gamma matrix with k rows
- * (slots per lane 2, 4, 8 or 16; heads_per_tile 0 = chosen from target_tiles). */
+ * (slots per lane 2, 4, 8 or 16; heads_per_tile 0 = chosen from target_tiles;
+ * widen != 0: rectangles with fewer heads than a tile take several lane blocks
+ * per tile, as in bz_min_distance's own tilings). */
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                              uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
+                              uint64_t target_tiles, uint32_t widen, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used);
 
 /* The prefixes a schedule BZ_SCHED_1..8 hands out at level g of a Gamma

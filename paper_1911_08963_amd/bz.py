@@ -78,7 +78,7 @@ class DebugRect(ctypes.Structure):
     _fields_ = [("lane_off", ctypes.c_uint32), ("lane_n", ctypes.c_uint32),
                 ("lane_t", ctypes.c_uint32), ("head_off", ctypes.c_uint32),
                 ("head_n", ctypes.c_uint32), ("head_t", ctypes.c_uint32),
-                ("_reserved0", ctypes.c_uint32), ("_reserved1", ctypes.c_uint32),
+                ("lane_mult", ctypes.c_uint32), ("_reserved1", ctypes.c_uint32),
                 ("lane_count", ctypes.c_uint64), ("head_count", ctypes.c_uint64),
                 ("tile_begin", ctypes.c_uint64), ("lane_blocks", ctypes.c_uint64),
                 ("head_blocks", ctypes.c_uint64), ("_reserved2", ctypes.c_uint64)]
@@ -133,7 +133,7 @@ def _signatures(lib):
         "bz_server_destroy": ([vp, ctypes.c_double], ctypes.c_int),
         "bz_debug_prepare_host": ([P(u64), u32, u32, u32, P(u32), P(u32), P(ctypes.c_int32),
                                    P(u64), u32, P(u32), ctypes.c_size_t], ctypes.c_int),
-        "bz_debug_plan_level": ([u32, u32, u32, u32, u64, P(DebugRect), u32, P(u32), P(u64),
+        "bz_debug_plan_level": ([u32, u32, u32, u32, u64, u32, P(DebugRect), u32, P(u32), P(u64),
                                  P(u32)], ctypes.c_int),
         "bz_debug_schedule": ([u32, u32, u32, u32, u32, u32, P(ctypes.c_int32), u64, P(u32), P(u64)],
                               ctypes.c_int),
@@ -571,12 +571,13 @@ def prepare_host(G, n: int):
     return soc, mf.value, km.value, gam[: nsets * k].copy(), packed
 
 
-def plan_level(k: int, g: int, slots: int = 8, heads_per_tile: int = 0, target_tiles: int = 1 << 17):
+def plan_level(k: int, g: int, slots: int = 8, heads_per_tile: int = 0, target_tiles: int = 1 << 17,
+               widen: bool = False):
     """bz_debug_plan_level: (list of rect dicts, total_tiles, heads_per_tile)."""
     cap = 16384
     rects = (DebugRect * cap)()
     nr, tt, hu = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
-    _check(lib().bz_debug_plan_level(k, g, slots, heads_per_tile, target_tiles, rects, cap,
+    _check(lib().bz_debug_plan_level(k, g, slots, heads_per_tile, target_tiles, int(widen), rects, cap,
                                      ctypes.byref(nr), ctypes.byref(tt), ctypes.byref(hu)))
     out = []
     for i in range(nr.value):

@@ -837,7 +837,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             if (!plans.count(t.key)) {
                 std::string err;
                 bz::LevelPlan p;
-                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err))
+                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err, true))
                     return fail(BZ_ELIMIT, err);
                 if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "a level's tiling needs more than the workspace's 16384 rectangles");
                 plans[t.key] = std::move(p);
@@ -853,10 +853,13 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     // once, then replays Alg. 1's bookkeeping on the read-back records. A
     // window ends at the task after which the bounds known when it starts
     // would already stop the search; tasks enqueued past the point where the
-    // device stops (U fell within the window) leave at once. Windows start at
-    // 2 tasks and double up to kChainMax; schedule tasks run one per window.
+    // device stops (U fell within the window) leave at once. Such a task costs
+    // a launch that returns at its first instruction (a few microseconds); a
+    // window's synchronisation, read-back and replay cost several times more,
+    // so windows start at 16 tasks and double up to kChainMax. Schedule tasks
+    // run one per window.
     uint32_t next_g = 1, next_j = 0;         // the next task in Alg. 1's order
-    uint32_t window = 2;
+    uint32_t window = 16;
     bool done = false;
     bool finished_in_one = false;            // the one launch ended the search (witness included)
     std::vector<Task> win;
@@ -1097,9 +1100,8 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                 const uint64_t blocks = (t.plan->total_tiles + 3) / 4;
                 const uint32_t grid =
                     (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
-                if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
-                BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
-                bz::ChainStep cs{};
+                // the task's bookkeeping step runs in its last work-group
+                bz::ChainStep &cs = a.step;
                 cs.state = d_state;
                 cs.key = a.key;
                 cs.ncomb = a.ncomb;
@@ -1109,7 +1111,8 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                 cs.cert_level = level_bound(t.g);
                 cs.level_stop = level_stop;
                 cs.stats = stats;
-                BZ_HIP(bz::launch_chain_step(cs, st));
+                if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
             }
         }
         if (ev1) BZ_HIP(hipEventRecord(ev1, st));
@@ -1337,13 +1340,13 @@ bz_status bz_debug_prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint3
 }
 
 bz_status bz_debug_plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                              uint64_t target_tiles, bz_debug_rect *rects, uint32_t cap,
+                              uint64_t target_tiles, uint32_t widen, bz_debug_rect *rects, uint32_t cap,
                               uint32_t *nrects, uint64_t *total_tiles, uint32_t *heads_used) {
     if (k == 0 || k > (uint32_t)bz::kMaxN || (slots != 2 && slots != 4 && slots != 8 && slots != 16))
         return fail(BZ_EINVAL, "bad k or slots");
     bz::LevelPlan p;
     std::string err;
-    if (!bz::plan_level(k, g, slots, heads_per_tile, target_tiles, p, err)) return fail(BZ_ELIMIT, err);
+    if (!bz::plan_level(k, g, slots, heads_per_tile, target_tiles, p, err, widen != 0)) return fail(BZ_ELIMIT, err);
     if (nrects) *nrects = (uint32_t)p.rects.size();
     if (total_tiles) *total_tiles = p.total_tiles;
     if (heads_used) *heads_used = p.heads_per_tile;

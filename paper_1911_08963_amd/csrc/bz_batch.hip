@@ -117,10 +117,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     switch (W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
     case WW * 2:                                                                                      \
-        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, sb, bt, rp, tile, lane);    \
+        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, nullptr, sb, bt, rp, tile, lane); \
         break;                                                                                        \
     case WW * 2 + 1:                                                                                  \
-        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, sb, bt, rp, tile, lane);     \
+        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, nullptr, sb, bt, rp, tile, lane);  \
         break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
@@ -357,10 +357,10 @@ __device__ __forceinline__ void one_tile(const OneArgs &a, const OneTask &T, uin
     switch (T.W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
     case WW * 2:                                                                                      \
-        run_tile<WW, slots_for_w(WW), false, STATS>(t, rc, binom_c, srow, sb, bt, rp, tile, lane);    \
+        run_tile<WW, slots_for_w(WW), false, STATS>(t, rc, binom_c, srow, nullptr, sb, bt, rp, tile, lane); \
         break;                                                                                        \
     case WW * 2 + 1:                                                                                  \
-        run_tile<WW, slots_for_w(WW), true, STATS>(t, rc, binom_c, srow, sb, bt, rp, tile, lane);     \
+        run_tile<WW, slots_for_w(WW), true, STATS>(t, rc, binom_c, srow, nullptr, sb, bt, rp, tile, lane);  \
         break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
@@ -1015,6 +1015,7 @@ __global__ __launch_bounds__(kBlock) void bz_batch_recover_kernel(BatchArgs b) {
     const Rect R = rects[lo];
     const uint64_t local = tile - R.tile_begin;
     const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
+    // batch and serving tilings keep one lane block per tile (lane_mult 1)
     const uint32_t lane_items = kWaveSize * slots_for_w(W);
     const uint64_t q0 = lb * lane_items;
     const uint32_t nl = (uint32_t)((R.lane_count - q0) < lane_items ? (R.lane_count - q0) : lane_items);

@@ -24,6 +24,9 @@ __global__ __launch_bounds__(kBlock) void bz_collect_kernel(CollectArgs a) {
         sbin[i] = a.binom[x * (kBinomT + 1) + y];
     }
     for (uint32_t i = threadIdx.x; i < a.k * W; i += blockDim.x) srow[i] = a.rows[i];
+    uint32_t *spx = srow + a.k * W;                      // (k+1) x W prefix XORs
+    __syncthreads();
+    build_prefix_xor<W>(srow, spx, a.k);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
@@ -36,36 +39,40 @@ __global__ __launch_bounds__(kBlock) void bz_collect_kernel(CollectArgs a) {
     for (uint64_t it = first; it < a.total_tiles; it += stride) {
         const uint64_t tile = uni64(it);
         const TileGeom t = locate_tile(a.nrects, rect_p, tile);
-        uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS], none[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) none[w] = 0;
-        const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, none, 0u, P, low, pen);
         const uint64_t h0 = t.hb * a.heads_per_tile;
         const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
-        const uint64_t base = t.lb * (kWaveSize * SLOTS);
-        head_walk<W, true>(t, rows, binom_c, a.k_low, h0, count,
-                           [&](const uint32_t (&H)[W], uint32_t hl, uint32_t step) {
-            uint32_t hit = 0;
+        uint64_t nvalid = 0;
+        for (uint32_t sb = 0; sb < t.lane_mult; ++sb) {
+            const uint64_t base = (t.lb * t.lane_mult + sb) * (uint64_t)(kWaveSize * SLOTS);
+            if (base >= t.lane_count) break;
+            uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS], none[W];
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                uint32_t v = bcnt_acc_s(H[0] ^ P[s][0], hl);
+            for (int w = 0; w < W; ++w) none[w] = 0;
+            nvalid += lane_setup<W, SLOTS>(t, base, a.k_low, srow, spx, sbin, bt, lane, none, 0u, P, low, pen);
+            head_walk<W, true>(t, rows, binom_c, a.k_low, h0, count,
+                               [&](const uint32_t (&H)[W], uint32_t hl, uint32_t step) {
+                uint32_t hit = 0;
 #pragma unroll
-                for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
-                hit |= (v + low[s] + pen[s] == a.target) ? (1u << s) : 0u;
-            }
-            if (__builtin_amdgcn_ballot_w64(hit != 0) == 0) return false;
-            for (int s = 0; s < SLOTS; ++s) {
-                if (!((hit >> s) & 1u)) continue;
-                const unsigned long long idx = atomicAdd(a.nhits, 1ull);
-                if (idx < a.cap) {
-                    CollectHit &o = a.hits[idx];
-                    o.tile = tile;
-                    o.q = base + (uint64_t)lane * SLOTS + s;
-                    o.h = h0 + step;
+                for (int s = 0; s < SLOTS; ++s) {
+                    uint32_t v = bcnt_acc_s(H[0] ^ P[s][0], hl);
+#pragma unroll
+                    for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
+                    hit |= (v + low[s] + pen[s] == a.target) ? (1u << s) : 0u;
                 }
-            }
-            return false;
-        });
+                if (__builtin_amdgcn_ballot_w64(hit != 0) == 0) return false;
+                for (int s = 0; s < SLOTS; ++s) {
+                    if (!((hit >> s) & 1u)) continue;
+                    const unsigned long long idx = atomicAdd(a.nhits, 1ull);
+                    if (idx < a.cap) {
+                        CollectHit &o = a.hits[idx];
+                        o.tile = tile;
+                        o.q = base + (uint64_t)lane * SLOTS + s;
+                        o.h = h0 + step;
+                    }
+                }
+                return false;
+            });
+        }
         if (lane == 0) atomicAdd(a.ncomb, (unsigned long long)nvalid * count);
     }
 }
@@ -77,7 +84,7 @@ static hipError_t launch_collect_w(const CollectArgs &a, uint32_t grid, size_t l
 }
 
 hipError_t launch_collect(const CollectArgs &a, uint32_t W, uint32_t grid, hipStream_t st) {
-    const size_t lds = (size_t)(a.k + 1) * (a.g + 1) * sizeof(uint64_t) + (size_t)a.k * W * sizeof(uint32_t);
+    const size_t lds = (size_t)(a.k + 1) * (a.g + 1) * sizeof(uint64_t) + (size_t)(2 * a.k + 1) * W * sizeof(uint32_t);
     switch (W) {
 #define BZ_COLLECT(WW) \
     case WW: return launch_collect_w<WW, slots_for_w(WW)>(a, grid, lds, st);

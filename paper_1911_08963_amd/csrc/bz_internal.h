@@ -51,12 +51,15 @@ constexpr double kSmallLevelComb = 16777216.0;    // 2^24: at most 8 slots
 // One product of two colex subset spaces inside the g-subsets of [0, k):
 // every union of a lane_t-subset of [lane_off, lane_off + lane_n) and a
 // head_t-subset of [head_off, head_off + head_n). The two ranges are disjoint.
+// A tile is lane_mult consecutive blocks of 64 * slots lane subsets by
+// heads_per_tile head steps: a rectangle with fewer heads than that takes
+// several lane blocks per tile, so that the tiles of a level cost about the same.
 struct Rect {
     uint32_t lane_off, lane_n, lane_t, head_off;
-    uint32_t head_n, head_t, _r0, _r1;
+    uint32_t head_n, head_t, lane_mult, _r1;
     uint64_t lane_count, head_count;   // C(lane_n, lane_t), C(head_n, head_t)
     uint64_t tile_begin;               // first tile index of this rectangle
-    uint64_t lane_blocks, head_blocks; // tiles along each factor
+    uint64_t lane_blocks, head_blocks; // tiles along each factor (lane: blocks of lane_mult)
     uint64_t _r2;
 };
 static_assert(sizeof(Rect) == 80, "Rect is 80 bytes");
@@ -73,8 +76,10 @@ struct LevelPlan {
     std::vector<Rect> rects;
 };
 
+// widen: rectangles with fewer heads than a tile holds take several lane
+// blocks per tile (lane_mult); otherwise lane_mult is 1.
 bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                uint64_t target_tiles, LevelPlan &out, std::string &err);
+                uint64_t target_tiles, LevelPlan &out, std::string &err, bool widen = false);
 
 // A code's smallest levels run in one launch of a single work-group
 // (bz_one_kernel): the levels of at most kOneLaunchComb sums, tasks small
@@ -100,7 +105,7 @@ struct OneTask {
 static_assert(sizeof(OneTask) == 64, "OneTask is 64 bytes");
 // The same for the g-subsets of rows [lo, lo + n) (plan_level is lo = 0, n = k).
 bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                uint64_t target_tiles, LevelPlan &out, std::string &err);
+                uint64_t target_tiles, LevelPlan &out, std::string &err, bool widen = false);
 
 // C(a, b) with saturation at kBinomSat for values >= 2^63.
 uint64_t binom_sat(uint32_t a, uint32_t b);

@@ -47,7 +47,7 @@ struct TaskArgs {
     unsigned long long *key;     // (min weight << 55) | tile, atomicMin
     unsigned long long *stats;   // (min << 55) | count, statistics mode
     unsigned long long *ncomb;   // combinations enumerated
-    unsigned long long *tile_ctr;   // reserved (tiles are assigned statically)
+    unsigned long long *tile_ctr;   // schedules: claim counter; enumeration with a step: work-groups done
     const uint32_t *cancel;      // host-visible cancel word, or null
     uint32_t nrects, k, k_low, g;
     uint32_t heads_per_tile;
@@ -55,6 +55,8 @@ struct TaskArgs {
     uint32_t u_prev;             // upper bound from completed tasks
     uint32_t exit_at;            // stop when the upper bound is <= this (0 = never)
     const ChainState *chain;     // when set: u_prev and exit_at come from here, and a stopped search skips the task
+    ChainStep step;              // when step.state is set: the last work-group to leave applies the task's
+                                 // bookkeeping step (counting the work-groups in tile_ctr, zero at the start)
 };
 
 struct RecoverArgs {
@@ -292,7 +294,6 @@ hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
 // and zeroes *clear (the witness flag) when it is set.
 hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState *state, const ChainState &init,
                              unsigned int *clear, hipStream_t st);
-hipError_t launch_chain_step(const ChainStep &s, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
 
 // ---- the paper's prefix-task schedules (bz_sched.hip, bz_sched.h)

@@ -9,8 +9,9 @@
 // needed inside one task). Before each tile a wave reads the task key and
 // stops when the upper bound has reached the certified lower bound (fast mode
 // only) or when the caller's cancel word is set. A wave keeps its combination
-// count and statistics word in LDS and adds them to the task's words once,
-// when it leaves.
+// count and statistics word in LDS; the work-group adds them to the task's
+// words once, when it leaves, and the last work-group to leave applies Alg. 1's
+// bookkeeping for the task to the window's state (no launch of its own).
 #include <hip/hip_runtime.h>
 
 #include "bz_internal.h"
@@ -18,6 +19,28 @@
 #include "bz_tile.h"
 
 namespace bz {
+
+// Alg. 1's bookkeeping after one task of a window, on the device: lower U by
+// the task's minimum, and, when the task is complete, raise the certified
+// bound (and at the level's end Alg. 1's L) and stop once L reaches U. A task
+// that is not complete ended early (certified bound reached, or canceled): the
+// search stops. The host replays the same steps on the read-back records.
+__device__ void chain_step_apply(const ChainStep &s, unsigned long long key, unsigned long long ncomb) {
+    ChainState c = *s.state;
+    if (c.done) return;
+    const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
+    c.U = min(c.U, tmin);
+    if (ncomb != s.total) {
+        c.done = 1;
+    } else {
+        c.Lcert = max(c.Lcert, s.cert_task);
+        c.exit_at = s.stats ? 0u : c.Lcert;
+        if (!s.level_stop) c.L = max(c.L, c.Lcert);
+        if (s.last_of_level) c.L = max(c.L, s.cert_level);
+        if ((!s.level_stop || s.last_of_level) && c.L >= c.U) c.done = 1;
+    }
+    *s.state = c;
+}
 
 template <int W, int SLOTS, bool PARTIAL, bool STATS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS || PARTIAL) ? 1 : 5))) void bz_enum_kernel(TaskArgs a) {
@@ -38,6 +61,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
         sbin[i] = a.binom[x * (kBinomT + 1) + y];
     }
     for (uint32_t i = threadIdx.x; i < a.k * W; i += blockDim.x) srow[i] = a.rows[i];
+    uint32_t *spx = srow + a.k * W;                      // (k+1) x W prefix XORs
+    __syncthreads();
+    build_prefix_xor<W>(srow, spx, a.k);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
@@ -75,13 +101,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
             stop = stop || uni(cv) != 0u;
         }
         if (stop) break;
-        run_tile<W, SLOTS, PARTIAL, STATS>(t, rows, binom_c, srow, sbin, bt, rect_p, tile, lane);
+        run_tile<W, SLOTS, PARTIAL, STATS>(t, rows, binom_c, srow, spx, sbin, bt, rect_p, tile, lane);
     }
-    if (lane == 0 && wave_words[wv][0]) {
-        atomicAdd(a.ncomb, wave_words[wv][0]);
-        if (STATS) {
-            const unsigned long long sw = wave_words[wv][1];
-            stats_merge(a.stats, (uint32_t)(sw >> kCountBits), sw & kCountMask);
+    // One global atomic per work-group, not per wave: when the waves of a
+    // short level end together, atomics on the same word queue up at the
+    // memory side (measured: the last of 2,441 waves of a C(64,6) level waited
+    // 12-19 us there).
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long nc = 0;
+        uint32_t smin = 0xffffffffu;
+        uint64_t scnt = 0;
+        for (uint32_t w = 0; w < kBlock / kWaveSize; ++w) {
+            nc += wave_words[w][0];
+            const unsigned long long sw = wave_words[w][1];
+            if (STATS && wave_words[w][0] && sw != ~0ull) {
+                const uint32_t m = (uint32_t)(sw >> kCountBits);
+                if (m < smin) { smin = m; scnt = sw & kCountMask; }
+                else if (m == smin) scnt += sw & kCountMask;
+            }
+        }
+        if (nc) {
+            atomicAdd(a.ncomb, nc);
+            if (STATS && smin != 0xffffffffu) stats_merge(a.stats, smin, scnt);
+        }
+        if (a.step.state) {
+            // the last work-group to leave applies the task's bookkeeping step,
+            // in place of a launch of its own: every other work-group's
+            // atomics are ordered before its count (release), and read after
+            // the last count (acquire)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned long long left = atomicAdd(a.tile_ctr, 1ull);
+            if (left + 1 == gridDim.x) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                chain_step_apply(a.step, __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                 __hip_atomic_load(a.ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
         }
     }
 }
@@ -114,39 +169,16 @@ __global__ void bz_chain_init_kernel(unsigned long long *records, uint32_t n, Ch
     if (i == 1 && clear) *clear = 0u;
 }
 
-// Alg. 1's bookkeeping after one task of a window, on the device: lower U by
-// the task's minimum, and, when the task is complete, raise the certified
-// bound (and at the level's end Alg. 1's L) and stop once L reaches U. A task
-// that is not complete ended early (certified bound reached, or canceled): the
-// search stops. The host replays the same steps on the read-back records.
-__global__ void bz_chain_step_kernel(ChainStep s) {
-    if (threadIdx.x != 0) return;
-    ChainState c = *s.state;
-    if (c.done) return;
-    const unsigned long long key = *s.key;
-    const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
-    c.U = min(c.U, tmin);
-    if (*s.ncomb != s.total) {
-        c.done = 1;
-    } else {
-        c.Lcert = max(c.Lcert, s.cert_task);
-        c.exit_at = s.stats ? 0u : c.Lcert;
-        if (!s.level_stop) c.L = max(c.L, c.Lcert);
-        if (s.last_of_level) c.L = max(c.L, s.cert_level);
-        if ((!s.level_stop || s.last_of_level) && c.L >= c.U) c.done = 1;
-    }
-    *s.state = c;
-}
-
 // Witness recovery: one thread per combination of the winning tile, each
 // computed from scratch (no shared state with the enumeration kernel), joined
 // to the rows of the tile's prefix task when it has one. The first thread
 // whose combination has the target weight writes its row indices and the
 // codeword (XOR of the full rows, original coordinates).
 __global__ void bz_recover_kernel(RecoverArgs a) {
-    const uint64_t lane_items = (uint64_t)kWaveSize * a.slots;
-    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Rect R = a.rect;
+    // the tile's lane subsets: lane_mult blocks of 64 * slots
+    const uint64_t lane_items = (uint64_t)kWaveSize * a.slots * (R.lane_mult ? R.lane_mult : 1u);
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t local = a.tile - R.tile_begin;
     const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
     const uint64_t li = id % lane_items, hs = id / lane_items;
@@ -230,7 +262,7 @@ static hipError_t launch_w(const TaskArgs &a, uint32_t slots, bool partial, bool
 
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st) {
-    const size_t lds = (size_t)(a.k + 1) * (a.g + 1) * sizeof(uint64_t) + (size_t)a.k * W * sizeof(uint32_t);
+    const size_t lds = enum_lds_bytes(a.k, a.g, W);
     switch (W) {
     case 1: return launch_w<1>(a, slots, partial, stats, grid, lds, st);
     case 2: return launch_w<2>(a, slots, partial, stats, grid, lds, st);
@@ -245,7 +277,8 @@ hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool parti
 }
 
 size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W) {
-    return (size_t)(k + 1) * (g + 1) * sizeof(uint64_t) + (size_t)k * W * sizeof(uint32_t);
+    // binomials, rows, prefix XORs of the rows
+    return (size_t)(k + 1) * (g + 1) * sizeof(uint64_t) + (size_t)(2 * k + 1) * W * sizeof(uint32_t);
 }
 
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats, unsigned long long *ncomb,
@@ -261,13 +294,9 @@ hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState
     return hipGetLastError();
 }
 
-hipError_t launch_chain_step(const ChainStep &s, hipStream_t st) {
-    hipLaunchKernelGGL(bz_chain_step_kernel, dim3(1), dim3(64), 0, st, s);
-    return hipGetLastError();
-}
-
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st) {
-    const uint64_t total = (uint64_t)kWaveSize * a.slots * a.heads_per_tile;
+    const uint64_t total =
+        (uint64_t)kWaveSize * a.slots * (a.rect.lane_mult ? a.rect.lane_mult : 1u) * a.heads_per_tile;
     const uint32_t grid = (uint32_t)((total + 255) / 256);
     hipLaunchKernelGGL(bz_recover_kernel, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();

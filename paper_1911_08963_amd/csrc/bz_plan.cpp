@@ -71,13 +71,18 @@ struct Builder {
 
 }  // namespace
 
+// The lane setup of one lane block (first subset unranked, successor steps
+// for the other slots) in units of one head step of the tile loop: about 850
+// instructions against 80 per head step for k = 64, W = 2, 16 slots.
+constexpr uint64_t kSetupHeads = 12;
+
 bool plan_level(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                uint64_t target_tiles, LevelPlan &out, std::string &err) {
-    return plan_range(0, k, g, slots, heads_per_tile, target_tiles, out, err);
+                uint64_t target_tiles, LevelPlan &out, std::string &err, bool widen) {
+    return plan_range(0, k, g, slots, heads_per_tile, target_tiles, out, err, widen);
 }
 
 bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t heads_per_tile,
-                uint64_t target_tiles, LevelPlan &out, std::string &err) {
+                uint64_t target_tiles, LevelPlan &out, std::string &err, bool widen) {
     out = LevelPlan{};
     out.k = lo + n; out.g = g; out.slots = slots;
     if (g == 0 || g > n) { err = "level out of range"; return false; }
@@ -103,6 +108,16 @@ bool plan_range(uint32_t lo, uint32_t n, uint32_t g, uint32_t slots, uint32_t he
             uint64_t lb = (r.lane_count + lane_items - 1) / lane_items;
             uint64_t hb = (r.head_count + ht - 1) / ht;
             if (lb >= kMaxTiles) { err = "level too large for the tile index"; return false; }
+            // a rectangle of few heads (a factor of one or two rows) would
+            // otherwise give tiles a fraction of the others' cost: on a level
+            // of about one tile per wave the waves holding full tiles then
+            // decide the launch's length. A lane block costs its setup (about
+            // kSetupHeads head steps) plus its heads.
+            uint64_t m = 1;
+            if (widen && r.head_count < ht)
+                m = std::max<uint64_t>(1, std::min<uint64_t>(lb, (ht + kSetupHeads) / (r.head_count + kSetupHeads)));
+            r.lane_mult = (uint32_t)m;
+            lb = (lb + m - 1) / m;
             r.lane_blocks = lb;
             r.head_blocks = hb;
             r.tile_begin = tiles;

@@ -36,6 +36,9 @@ __global__ __launch_bounds__(kBlock) void bz_sched_kernel(SchedArgs s) {
         sbin[i] = a0.binom[x * (kBinomT + 1) + y];
     }
     for (uint32_t i = threadIdx.x; i < a0.k * W; i += blockDim.x) srow[i] = a0.rows[i];
+    uint32_t *spx = srow + a0.k * W;                     // (k+1) x W prefix XORs
+    __syncthreads();
+    build_prefix_xor<W>(srow, spx, a0.k);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void bz_sched_kernel(SchedArgs s) {
         cptr_rect rp = rects + plans[lo].rect_off;
         for (uint64_t tile = 0; tile < ntiles; ++tile) {
             if (stop_now()) return true;
-            run_tile_pre<W, SLOTS, PARTIAL, STATS, true>(a, rows, binom_c, srow, sbin, bt, rp, tile, lane, pre,
+            run_tile_pre<W, SLOTS, PARTIAL, STATS, true>(a, rows, binom_c, srow, spx, sbin, bt, rp, tile, lane, pre,
                                                          pre_low, task * s.stride + tile, &sum);
         }
         return false;
@@ -123,9 +126,7 @@ __global__ __launch_bounds__(kBlock) void bz_sched_kernel(SchedArgs s) {
 
 // ---------------------------------------------------------------- dispatch
 
-static size_t sched_lds(const SchedArgs &a, uint32_t W) {
-    return (size_t)(a.t.k + 1) * (a.t.g + 1) * sizeof(uint64_t) + (size_t)a.t.k * W * sizeof(uint32_t);
-}
+static size_t sched_lds(const SchedArgs &a, uint32_t W) { return enum_lds_bytes(a.t.k, a.t.g, W); }
 
 template <int W>
 static const void *sched_fn(bool partial, bool stats) {

@@ -148,8 +148,8 @@ __device__ __forceinline__ uint32_t colex_digit_s(cptr64 gb, uint32_t i, uint32_
 // Where a tile sits: its rectangle's two factors and the tile's block
 // coordinates along them (all uniform).
 struct TileGeom {
-    uint32_t lane_off, lane_n, lane_t, head_off, head_n, head_t;
-    uint64_t lane_count, head_count, lb, hb;
+    uint32_t lane_off, lane_n, lane_t, head_off, head_n, head_t, lane_mult;
+    uint64_t lane_count, head_count, lb, hb;   // lb: the tile's first lane block / lane_mult
 };
 
 __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_p, uint64_t tile) {
@@ -164,6 +164,7 @@ __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_
     t.head_off = rect_p[ri].head_off; t.head_n = rect_p[ri].head_n; t.head_t = rect_p[ri].head_t;
     t.lane_count = rect_p[ri].lane_count;
     t.head_count = rect_p[ri].head_count;
+    t.lane_mult = rect_p[ri].lane_mult ? rect_p[ri].lane_mult : 1u;
     const uint64_t head_blocks = rect_p[ri].head_blocks;
     const uint64_t local = tile - rect_p[ri].tile_begin;
     t.lb = local / head_blocks;
@@ -171,17 +172,43 @@ __device__ __forceinline__ TileGeom locate_tile(uint32_t nrects, cptr_rect rect_
     return t;
 }
 
-// The lane subsets of a tile: lane l, slot s holds the lane subset of colex
-// rank lb * 64 * SLOTS + l * SLOTS + s, so that a lane's slots are consecutive
+// The prefix XORs of k rows in LDS: spx[i * W + w] = XOR of srow[r * W + w]
+// over r < i, for i = 0..k, by an XOR scan across each wave (a wave per word).
+// The caller synchronises the work-group before and after.
+template <int W>
+__device__ void build_prefix_xor(const uint32_t *srow, uint32_t *spx, uint32_t k) {
+    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
+    const uint32_t nw = blockDim.x / kWaveSize;
+    for (uint32_t w = threadIdx.x / kWaveSize; w < (uint32_t)W; w += nw) {
+        uint32_t carry = 0;
+        for (uint32_t c = 0; c < k; c += kWaveSize) {
+            uint32_t v = (c + lane < k) ? srow[(c + lane) * W + w] : 0u;
+            for (uint32_t d = 1; d < kWaveSize; d <<= 1) {
+                const uint32_t o = __shfl_up(v, d, kWaveSize);
+                v ^= (lane >= d) ? o : 0u;
+            }
+            v ^= carry;
+            if (c + lane < k) spx[(c + lane + 1) * W + w] = v;
+            carry = __shfl(v, kWaveSize - 1, kWaveSize);
+        }
+        if (lane == 0) spx[w] = 0;
+    }
+}
+
+// The lane subsets of one lane block of a tile: lane l, slot s holds the lane
+// subset of colex rank base + l * SLOTS + s, so that a lane's slots are consecutive
 // ranks. P[s] is the XOR of its rows, low[s] the number of its rows below
 // k_low, pen[s] = 0x10000 when the rank is past the factor's end. Returns the
 // number of valid lane subsets (uniform).
 // A lane unranks its first subset (colex digits, binomials from sbin) and
 // reaches the next ones by colex successor steps on a 64-bit mask of the lane
-// range (Gosper's step), XORing only the rows that change, about two per step.
+// range (Gosper's step). The rows a step changes form two intervals of the
+// range, so with the prefix XORs of the rows (spx: spx[i * W + w] is the XOR of
+// rows 0..i-1) a step costs four look-ups; without them (spx null) the lane
+// XORs the changed rows one by one, a loop whose length depends on the lane.
 // A lane range wider than 64 rows unranks every slot instead.
-// No branch depends on the lane except the loop over a step's changed rows: a
-// lane past the end unranks rank 0 and is masked by pen. (With an "if (valid)"
+// No other branch depends on the lane: a lane past the end unranks rank 0 and
+// is masked by pen. (With an "if (valid)"
 // per lane around the unranking the optimizer once specialised the tile's
 // uniform combination count per divergent path and the wave took the wrong
 // path's value.)
@@ -211,12 +238,12 @@ __device__ __forceinline__ uint64_t unrank_lane(const TileGeom &t, uint64_t r, c
 }
 
 template <int W, int SLOTS>
-__device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low, const uint32_t *srow,
-                                               const uint64_t *sbin, uint32_t bt, uint32_t lane,
-                                               const uint32_t (&pre)[W], uint32_t pre_low,
+__device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint64_t base, uint32_t k_low,
+                                               const uint32_t *srow, const uint32_t *spx,
+                                               const uint64_t *sbin, uint32_t bt,
+                                               uint32_t lane, const uint32_t (&pre)[W], uint32_t pre_low,
                                                uint32_t (&P)[SLOTS][W], uint32_t (&low)[SLOTS],
                                                uint32_t (&pen)[SLOTS]) {
-    const uint64_t base = t.lb * (kWaveSize * SLOTS);
     const uint32_t nvalid =
         uni(t.lane_count > base ? (uint32_t)umin64(t.lane_count - base, (uint64_t)kWaveSize * SLOTS) : 0u);
     float lf_top = 0.f;                            // log2(lane_t!)
@@ -234,6 +261,9 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
         for (int w = 0; w < W; ++w) cur[w] = pre[w];
         uint64_t x = unrank_lane<W>(t, q0 < t.lane_count ? q0 : 0ull, srow, sbin, bt, lf_top, cur);
         const uint64_t range = t.lane_n >= 64 ? ~0ull : ((1ull << t.lane_n) - 1);
+        uint32_t px0[W];                           // prefix XOR below the range
+#pragma unroll
+        for (int w = 0; w < W; ++w) px0[w] = spx ? spx[t.lane_off * W + w] : 0u;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
@@ -241,19 +271,33 @@ __device__ __forceinline__ uint32_t lane_setup(const TileGeom &t, uint32_t k_low
             low[s] = pre_low + (uint32_t)__builtin_popcountll(x & low_mask);
             pen[s] = (q0 + (uint64_t)s < t.lane_count) ? 0u : 0x10000u;
             if (s + 1 < SLOTS) {
-                // colex successor: the lowest run of ones moves up by one, the rest of it drops to the bottom
+                // colex successor: the lowest run of ones, bits p..top-1, moves its
+                // top bit to top and the rest of it to the bottom
                 const uint64_t u = x & (~x + 1);
                 const uint64_t v = x + u;
-                const uint64_t nx = v | (((v ^ x) >> 2) >> __builtin_ctzll(x | (1ull << 63)));
+                const uint32_t p = (uint32_t)__builtin_ctzll(x | (1ull << 63));
+                const uint64_t nx = v | (((v ^ x) >> 2) >> p);
                 // past the last subset of the range the slots are masked: keep the sum
                 const bool ok = v != 0 && (nx & ~range) == 0;
-                uint64_t diff = ok ? (x ^ nx) : 0ull;
-                while (diff) {
-                    const uint32_t b = (uint32_t)__builtin_ctzll(diff);
-                    diff &= diff - 1;
-                    const uint32_t row = t.lane_off + b;
+                if (spx) {
+                    // the rows that change are the intervals [p, top] and [0, top - p - 2]
+                    // of the range: four prefix XORs, no lane-dependent loop
+                    const uint32_t top = 63u - (uint32_t)__builtin_clzll((v ^ x) | 1ull);
+                    const uint32_t i1 = ok ? t.lane_off + top + 1 : t.lane_off;
+                    const uint32_t i2 = ok ? t.lane_off + p : t.lane_off;
+                    const uint32_t i3 = ok ? t.lane_off + top - p - 1 : t.lane_off;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) cur[w] ^= srow[row * W + w];
+                    for (int w = 0; w < W; ++w)
+                        cur[w] ^= spx[i1 * W + w] ^ spx[i2 * W + w] ^ spx[i3 * W + w] ^ px0[w];
+                } else {
+                    uint64_t diff = ok ? (x ^ nx) : 0ull;
+                    while (diff) {
+                        const uint32_t b = (uint32_t)__builtin_ctzll(diff);
+                        diff &= diff - 1;
+                        const uint32_t row = t.lane_off + b;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) cur[w] ^= srow[row * W + w];
+                    }
                 }
                 x = ok ? nx : x;
             }
@@ -401,69 +445,77 @@ struct TileSum {
 // the same word would serialise the waves).
 template <int W, int SLOTS, bool PARTIAL, bool STATS, bool DEFER = false>
 __device__ __forceinline__ void run_tile_pre(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
-                                             const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
+                                             const uint32_t *srow, const uint32_t *spx,
+                                             const uint64_t *sbin, uint32_t bt,
                                              cptr_rect rect_p, uint64_t tile, uint32_t lane,
                                              const uint32_t (&pre)[W], uint32_t pre_low, uint64_t key_tile,
                                              TileSum *sum = nullptr) {
     const TileGeom t = locate_tile(a.nrects, rect_p, tile);
-    uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS];
-    const uint32_t nvalid = lane_setup<W, SLOTS>(t, a.k_low, srow, sbin, bt, lane, pre, pre_low, P, low, pen);
     const uint64_t h0 = t.hb * a.heads_per_tile;
     const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
-    const uint64_t tile_comb = (uint64_t)nvalid * count;
-
+    uint64_t nvalid = 0;                         // lane subsets of the tile (uniform)
     uint32_t m = 0xffffffffu;                    // full: running minimum of all slots
-    uint32_t ms[SLOTS], cs[SLOTS];               // partial or statistics: per slot
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) { ms[s] = 0xffffffffu; cs[s] = 0; }
+    uint32_t lane_best = 0xffffffffu;            // partial or statistics: the lane's best weight
+    uint32_t lane_cnt = 0;
+    // the tile's lane blocks, each against the same walk over the heads
+    for (uint32_t sb = 0; sb < t.lane_mult; ++sb) {
+        const uint64_t base = (t.lb * t.lane_mult + sb) * (uint64_t)(kWaveSize * SLOTS);
+        if (base >= t.lane_count) break;         // uniform: the rectangle's last lane block is done
+        uint32_t P[SLOTS][W], low[SLOTS], pen[SLOTS];
+        nvalid += lane_setup<W, SLOTS>(t, base, a.k_low, srow, spx, sbin, bt, lane, pre, pre_low, P, low, pen);
 
-    head_walk<W, PARTIAL>(t, rows, binom_c, a.k_low, h0, count,
-                          [&](const uint32_t (&H)[W], uint32_t hl, uint32_t) {
-        if (!PARTIAL && !STATS) {
-            uint32_t acc[SLOTS];
+        uint32_t ms[SLOTS], cs[SLOTS];           // partial or statistics: per slot
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                uint32_t v = bcnt_acc(H[0] ^ P[s][0], pen[s]);
+        for (int s = 0; s < SLOTS; ++s) { ms[s] = 0xffffffffu; cs[s] = 0; }
+
+        head_walk<W, PARTIAL>(t, rows, binom_c, a.k_low, h0, count,
+                              [&](const uint32_t (&H)[W], uint32_t hl, uint32_t) {
+            if (!PARTIAL && !STATS) {
+                uint32_t acc[SLOTS];
 #pragma unroll
-                for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
-                acc[s] = v;
-            }
+                for (int s = 0; s < SLOTS; ++s) {
+                    uint32_t v = bcnt_acc(H[0] ^ P[s][0], pen[s]);
 #pragma unroll
-            for (int s = 0; s < SLOTS; s += 2) m = min3u(m, acc[s], acc[s + 1]);
-        } else {
+                    for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
+                    acc[s] = v;
+                }
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                uint32_t v = bcnt_acc_s(H[0] ^ P[s][0], hl);
+                for (int s = 0; s < SLOTS; s += 2) m = min3u(m, acc[s], acc[s + 1]);
+            } else {
 #pragma unroll
-                for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
-                if (STATS) {
-                    cs[s] = (v < ms[s]) ? 0u : cs[s];
-                    ms[s] = min(ms[s], v);
-                    cs[s] += (v == ms[s]) ? 1u : 0u;
-                } else {
-                    ms[s] = min(ms[s], v);
+                for (int s = 0; s < SLOTS; ++s) {
+                    uint32_t v = bcnt_acc_s(H[0] ^ P[s][0], hl);
+#pragma unroll
+                    for (int w = 1; w < W; ++w) v = bcnt_acc(H[w] ^ P[s][w], v);
+                    if (STATS) {
+                        cs[s] = (v < ms[s]) ? 0u : cs[s];
+                        ms[s] = min(ms[s], v);
+                        cs[s] += (v == ms[s]) ? 1u : 0u;
+                    } else {
+                        ms[s] = min(ms[s], v);
+                    }
                 }
             }
+            return false;
+        });
+
+        if (PARTIAL || STATS) {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                if (pen[s]) continue;
+                // full-rank statistics: head weight hl was 0, add the whole identity part g
+                const uint32_t wgt = PARTIAL ? ms[s] + low[s] : ms[s] + a.g;
+                if (wgt < lane_best) { lane_best = wgt; lane_cnt = STATS ? cs[s] : 0; }
+                else if (STATS && wgt == lane_best) lane_cnt += cs[s];
+            }
         }
-        return false;
-    });
+    }
+    const uint64_t tile_comb = nvalid * count;
 
     // ---- end of tile: weights, wave reduction, atomics
-    uint32_t lane_best;
-    uint32_t lane_cnt = 0;
     if (!PARTIAL && !STATS) {
         lane_best = m + a.g;                     // identity part of a full-rank Gamma_j
         if (m >= 0x10000u) lane_best = 0xffffffffu;
-    } else {
-        lane_best = 0xffffffffu;
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            if (pen[s]) continue;
-            // full-rank statistics: head weight hl was 0, add the whole identity part g
-            const uint32_t wgt = PARTIAL ? ms[s] + low[s] : ms[s] + a.g;
-            if (wgt < lane_best) { lane_best = wgt; lane_cnt = STATS ? cs[s] : 0; }
-            else if (STATS && wgt == lane_best) lane_cnt += cs[s];
-        }
     }
     const uint32_t tmin = uni(wave_min(lane_best));
     uint32_t tcnt = 0;
@@ -483,17 +535,18 @@ __device__ __forceinline__ void run_tile_pre(const TaskArgs &a, cptr32 rows, cpt
 // A tile of the task's own tiling (no prefix).
 template <int W, int SLOTS, bool PARTIAL, bool STATS>
 __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
-                                         const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
-                                         cptr_rect rect_p, uint64_t tile, uint32_t lane) {
+                                         const uint32_t *srow, const uint32_t *spx, const uint64_t *sbin,
+                                         uint32_t bt, cptr_rect rect_p, uint64_t tile, uint32_t lane) {
     uint32_t none[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) none[w] = 0;
-    run_tile_pre<W, SLOTS, PARTIAL, STATS>(a, rows, binom_c, srow, sbin, bt, rect_p, tile, lane, none, 0u, tile);
+    run_tile_pre<W, SLOTS, PARTIAL, STATS>(a, rows, binom_c, srow, spx, sbin, bt, rect_p, tile, lane, none, 0u,
+                                           tile);
 }
 
 // Finds one combination of the tile whose weight is target (the tile is
-// known to hold one). The lane subsets are taken one slot at a time (slot s:
-// ranks lb * 64 * SLOTS + lane * SLOTS + s), each against a walk over the tile's
+// known to hold one). The lane subsets are taken one slot at a time (slot s of
+// lane block b: ranks b * 64 * SLOTS + lane * SLOTS + s), each against a walk over the tile's
 // heads; after each head step a ballot tells whether any lane hit. Returns
 // (uniform) true and, in every lane, the lane-subset rank and head rank of the
 // first hit. Few registers: this runs inside the resident serving kernel.
@@ -506,8 +559,10 @@ __device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cpt
     const uint64_t h0 = t.hb * a.heads_per_tile;
     const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
     bool found = false;
-    for (int s = 0; s < SLOTS && !found; ++s) {
-        const uint64_t base = t.lb * (kWaveSize * SLOTS) + (uint64_t)s;
+    const uint64_t nslots = (uint64_t)t.lane_mult * SLOTS;
+    for (uint64_t s = 0; s < nslots && !found; ++s) {
+        // slot s % SLOTS of lane block s / SLOTS of the tile
+        const uint64_t base = (t.lb * t.lane_mult + s / SLOTS) * (kWaveSize * SLOTS) + s % SLOTS;
         if (base >= t.lane_count) break;                // lane 0 past the end: every lane is
         const uint64_t q = base + (uint64_t)lane * SLOTS;
         const bool valid = q < t.lane_count;      // no lane-dependent branch (see lane_setup)

@@ -127,10 +127,40 @@ def test_plan_covers_every_subset_once(slots):
             assert got == list(itertools.combinations(range(k), g)), (k, g)
 
 
+@pytest.mark.parametrize("slots", [2, 16])
+def test_widened_tiles_cover_each_pair_once(slots):
+    """Walking the tiles as the kernels do (tile -> rectangle, lane block lb of
+    lane_mult blocks, head block hb) visits every (lane rank, head rank) pair of
+    every rectangle exactly once."""
+    widened = False
+    for k, g, ht in ((20, 5, 32), (24, 6, 64), (30, 4, 32), (17, 3, 32), (40, 4, 64)):
+        rects, tiles, used = bz.plan_level(k, g, slots=slots, heads_per_tile=ht, widen=True)
+        assert used == ht
+        items = 64 * slots
+        seen = {}
+        for tile in range(tiles):
+            ri = max(i for i, r in enumerate(rects) if r["tile_begin"] <= tile)
+            r = rects[ri]
+            local = tile - r["tile_begin"]
+            lb, hb = divmod(local, r["head_blocks"])
+            for sb in range(r["lane_mult"]):
+                base = (lb * r["lane_mult"] + sb) * items
+                if base >= r["lane_count"]:
+                    break
+                for q in range(base, min(base + items, r["lane_count"])):
+                    for h in range(hb * ht, min(hb * ht + ht, r["head_count"])):
+                        seen[(ri, q, h)] = seen.get((ri, q, h), 0) + 1
+        assert all(v == 1 for v in seen.values())
+        assert len(seen) == math.comb(k, g)
+        widened = widened or any(r["lane_mult"] > 1 for r in rects)
+    assert widened
+
+
+@pytest.mark.parametrize("widen", [False, True])
 @pytest.mark.parametrize("k,g", [(64, 7), (64, 11), (96, 12), (150, 9), (200, 6), (256, 8), (40, 20)])
-def test_plan_invariants(k, g):
+def test_plan_invariants(k, g, widen):
     for slots in (2, 4, 8, 16):
-        rects, tiles, ht = bz.plan_level(k, g, slots=slots)
+        rects, tiles, ht = bz.plan_level(k, g, slots=slots, target_tiles=8192, widen=widen)
         tot = 0
         tb = 0
         for r in rects:
@@ -146,7 +176,15 @@ def test_plan_invariants(k, g):
                 assert not (a & b)
             assert r["lane_off"] + r["lane_n"] <= k and r["head_off"] + r["head_n"] <= k
             assert r["tile_begin"] == tb
-            assert r["lane_blocks"] == -(-r["lane_count"] // (64 * slots))
+            # a tile: lane_mult blocks of 64 * slots lane subsets by ht heads, and no
+            # more lane subsets than ht full heads would give it
+            m = r["lane_mult"]
+            assert m >= 1 and (widen or m == 1)
+            assert m * min(r["head_count"], ht) <= ht or m == 1
+            if widen and r["head_count"] < ht:
+                # a lane block's setup counts as 12 head steps
+                assert m == max(1, min(-(-r["lane_count"] // (64 * slots)), (ht + 12) // (r["head_count"] + 12)))
+            assert r["lane_blocks"] == -(-(-(-r["lane_count"] // (64 * slots))) // m)
             assert r["head_blocks"] == -(-r["head_count"] // ht)
             tb += r["lane_blocks"] * r["head_blocks"]
             tot += r["lane_count"] * r["head_count"]
