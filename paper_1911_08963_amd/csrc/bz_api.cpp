@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -73,6 +74,7 @@ using bz::now_s;
 constexpr size_t kWsRecover = 384;     // flag, len (u32), codeword (4 x u64)
 constexpr size_t kWsIndices = 512;     // the witness's row indices: up to 384 u32 before kWsPreRows
 constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
+constexpr size_t kWsRecTasks = 2304;   // a window's tasks for its witness recovery (bz::RecoverTask)
 constexpr size_t kWsRects = 4096;
 constexpr size_t kMaxRects = 16384;
 constexpr uint32_t kChainMax = 32;
@@ -89,8 +91,34 @@ static_assert(sizeof(bz::ChainState) <= 128, "bounds fit their line");
 static_assert(kWsRecover + 8 + bz::kHostWords * sizeof(uint64_t) <= kWsIndices, "flag, length and codeword fit");
 static_assert(kWsPreRows - kWsIndices >= (size_t)bz::kBinomT * sizeof(uint32_t),
               "the recovered combination's row indices (g <= kBinomT) fit below the prefix rows");
-static_assert(kWsRects - kWsPreRows >= 64 * sizeof(uint32_t), "a prefix task's rows fit below the tilings");
+static_assert(kWsRecTasks - kWsPreRows >= 64 * sizeof(uint32_t), "a prefix task's rows fit below the window's tasks");
+static_assert(kWsRects - kWsRecTasks >= kChainMax * sizeof(bz::RecoverTask), "a window's tasks fit below the tilings");
 
+
+// A level's tiling depends on (k, g, lane sums, heads per tile, target tile
+// count) only: a process-wide cache keeps it for every later search of the
+// same shape (up to kPlanCacheBytes of rectangles; past that, tilings are
+// built per search).
+constexpr size_t kPlanCacheBytes = 64u << 20;
+std::shared_ptr<const bz::LevelPlan> cached_plan(uint32_t k, uint32_t g, uint32_t slots, uint32_t heads,
+                                                 uint64_t target, std::string &err) {
+    using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint64_t>;
+    static std::mutex mu;
+    static std::map<Key, std::shared_ptr<const bz::LevelPlan>> cache;
+    static size_t bytes = 0;
+    const Key key{k, g, slots, heads, target};
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    auto p = std::make_shared<bz::LevelPlan>();
+    if (!bz::plan_level(k, g, slots, heads, target, *p, err, true)) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    const size_t b = p->rects.size() * sizeof(bz::Rect);
+    if (bytes + b <= kPlanCacheBytes && cache.emplace(key, p).second) bytes += b;
+    return p;
+}
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
 // later matrices at level g-1 (j == m_f is the partial matrix).
@@ -110,6 +138,10 @@ uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t 
 // the process ends.
 constexpr size_t kStageBytes = 64 * 1024;
 constexpr size_t kPinnedBytes = kChainBytes + kStageBytes;
+// the staging area's tail: a window's tasks for the recovery, and before them
+// the recovery's read-back (flag and length, codeword)
+constexpr size_t kStageTasksOff = kStageBytes - kChainMax * sizeof(bz::RecoverTask);
+constexpr size_t kStageRecoverOff = kStageTasksOff - 64;
 static_assert(kOneBytes <= kChainBytes, "a one launch's state and records fit the read-back buffer");
 class PinnedWords {
   public:
@@ -502,6 +534,22 @@ bool build_one_launch(bz_code &c, std::vector<bz::Rect> &rects, std::string &err
     std::vector<uint32_t> first(c.one_plans.size(), 0);
     for (size_t pi = 1; pi < c.one_plans.size(); ++pi) first[pi] = first[pi - 1] + (uint32_t)c.one_plans[pi - 1].rects.size();
     for (size_t t = 0; t < c.one_tasks.size(); ++t) c.one_tasks[t].rect_off = first[c.one_plan_of[t]];
+    // The one launch pays off when its levels end the search; otherwise the
+    // search waits for it before its first window. It can end the search only if
+    // d is at most the bound its last level certifies. Against the weight where a
+    // random [n, k] code expects its first nonzero codeword (sum over w' <= w of
+    // C(n, w') 2^(k - n) reaches 1), allowing two below: a speed choice only,
+    // the result is the same either way.
+    if (!c.one_tasks.empty()) {
+        double acc = 0.0;
+        uint32_t w_est = 0;
+        while (w_est < c.n && acc < 1.0) {
+            ++w_est;
+            acc += std::exp(std::lgamma((double)c.n + 1) - std::lgamma((double)w_est + 1) -
+                            std::lgamma((double)(c.n - w_est) + 1) + ((double)k - (double)c.n) * std::log(2.0));
+        }
+        c.one_likely = c.one_tasks.back().cert_level + 2 >= w_est;
+    }
     return true;
 }
 
@@ -780,7 +828,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     }
 
     using PlanKey = std::tuple<uint32_t, uint32_t, uint32_t>;                  // (g, slots, tiles/wave)
-    std::map<PlanKey, bz::LevelPlan> plans;
+    std::map<PlanKey, std::shared_ptr<const bz::LevelPlan>> plans;
     // Tilings already on the device (rect offset in the workspace): a level's
     // tiling is uploaded once for all its Gamma_j. When the region is full it
     // starts over at a window's start; every earlier launch has finished by then.
@@ -836,13 +884,12 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             t.key = std::make_tuple(g, slots, per_wave);
             if (!plans.count(t.key)) {
                 std::string err;
-                bz::LevelPlan p;
-                if (!bz::plan_level(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, p, err, true))
-                    return fail(BZ_ELIMIT, err);
-                if (p.rects.size() > kMaxRects) return fail(BZ_ELIMIT, "a level's tiling needs more than the workspace's 16384 rectangles");
+                auto p = cached_plan(k, g, slots, opt.heads_per_tile, per_wave * resident_waves, err);
+                if (!p) return fail(BZ_ELIMIT, err);
+                if (p->rects.size() > kMaxRects) return fail(BZ_ELIMIT, "a level's tiling needs more than the workspace's 16384 rectangles");
                 plans[t.key] = std::move(p);
             }
-            t.plan = &plans[t.key];
+            t.plan = plans[t.key].get();
         }
         t.slots = slots;
         return BZ_OK;
@@ -862,6 +909,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     uint32_t window = 16;
     bool done = false;
     bool finished_in_one = false;            // the one launch ended the search (witness included)
+    bool witness_done = false;               // a window recovered the witness on the device
     std::vector<Task> win;
     std::vector<bz::Rect> staged;
     // ---- the smallest levels in one work-group (bz_one_kernel)
@@ -872,7 +920,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
     // same bookkeeping on the records. A search that is not over by then goes on
     // with windows of per-task launches below.
     uint32_t one_run = 0;
-    if (!use_sched && !(opt.flags & BZ_F_TASK_LAUNCHES))
+    if (!use_sched && !(opt.flags & BZ_F_TASK_LAUNCHES) && c->one_likely)
         for (const bz::OneTask &T : c->one_tasks)
             if (!opt.max_level || T.g <= opt.max_level) one_run++;
     if (one_run) {
@@ -1036,7 +1084,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         if (!staged.empty()) {
             const size_t off = placed.front().second, bytes = staged.size() * sizeof(bz::Rect);
             const void *src = staged.data();
-            if (bytes <= kStageBytes) {                 // the previous window's copies have finished
+            if (bytes <= kStageRecoverOff) {            // the previous window's copies have finished
                 std::memcpy(stage, staged.data(), bytes);
                 src = stage;
             }
@@ -1050,6 +1098,13 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         init.Lcert = Lcert;
         BZ_HIP(bz::launch_chain_init(d_records, (uint32_t)win.size(), d_state, init,
                                      want_witness ? (unsigned int *)(ws + kWsRecover) : nullptr, st));
+        // an enumeration window recovers its witness on the device when it
+        // ends the search: no further synchronisation after the read-back
+        const bool dev_recover = want_witness && !use_sched;
+        auto *rtasks = (bz::RecoverTask *)(stage + kStageTasksOff);
+        uint64_t rec_threads = 0;
+        const uint32_t U_start = U;
+        const bool have_start = best.have;
         for (size_t i = 0; i < win.size(); ++i) {
             const Task &t = win[i];
             unsigned long long *rec = d_records + i * bz::kRecWords;
@@ -1111,12 +1166,48 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                 cs.cert_level = level_bound(t.g);
                 cs.level_stop = level_stop;
                 cs.stats = stats;
+                if (dev_recover) {
+                    bz::RecoverTask &rt = rtasks[i];
+                    rt = bz::RecoverTask{};
+                    rt.rows = a.rows;
+                    rt.full_rows = (const uint64_t *)((char *)c->dev + c->dev_full_off) + (size_t)t.j * k * bz::kHostWords;
+                    rt.rects = a.rects;
+                    rt.nrects = a.nrects;
+                    rt.slots = t.slots;
+                    rt.heads_per_tile = a.heads_per_tile;
+                    rt.W = t.W;
+                    rt.k_low = a.k_low;
+                    uint32_t mult = 1;
+                    for (const bz::Rect &r : t.plan->rects) mult = std::max(mult, r.lane_mult);
+                    rec_threads = std::max<uint64_t>(rec_threads,
+                                                     (uint64_t)bz::kWaveSize * t.slots * mult * a.heads_per_tile);
+                }
                 if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
                 BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
             }
         }
         if (ev1) BZ_HIP(hipEventRecord(ev1, st));
+        if (dev_recover) {
+            BZ_HIP(hipMemcpyAsync(ws + kWsRecTasks, rtasks, win.size() * sizeof(bz::RecoverTask),
+                                  hipMemcpyHostToDevice, st));
+            bz::RecoverWindowArgs ra{};
+            ra.state = d_state;
+            ra.records = d_records;
+            ra.tasks = (const bz::RecoverTask *)(ws + kWsRecTasks);
+            ra.binom = dc.binom;
+            ra.flag = (unsigned int *)(ws + kWsRecover);
+            ra.indices_len = (uint32_t *)(ws + kWsRecover + 4);
+            ra.codeword = (unsigned long long *)(ws + kWsRecover + 8);
+            ra.indices = (uint32_t *)(ws + kWsIndices);
+            ra.ntasks = (uint32_t)win.size();
+            ra.U0 = U_start;
+            ra.have0 = have_start ? 1u : 0u;
+            BZ_HIP(bz::launch_recover_window(ra, rec_threads, st));
+        }
         BZ_HIP(hipMemcpyAsync(words, ws + kWsChain, 128 + win.size() * kRecBytes, hipMemcpyDeviceToHost, st));
+        if (dev_recover)
+            BZ_HIP(hipMemcpyAsync(stage + kStageRecoverOff, ws + kWsRecover, (1 + bz::kHostWords) * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, st));
         BZ_HIP(hipStreamSynchronize(st));
         if (ev0) {
             float ms = 0.f;
@@ -1125,6 +1216,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         }
 
         bool stopped = false;                  // L reached U at a level start inside the window
+        bool best_here = false;                // the winning tile is one of this window's
         for (size_t i = 0; i < win.size() && !done; ++i) {
             const Task &t = win[i];
             if (i > 0 && t.j == 0 && L >= U) { stopped = true; break; }
@@ -1145,6 +1237,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             res->stats_len++;
             if (tmin < U || (tmin == U && !best.have)) {
                 U = tmin;
+                best_here = true;
                 best.have = true; best.j = j; best.g = g; best.tile = r[bz::kRecKey] & bz::kTileMask;
                 best.slots = slots;
                 const bz::Rect *rr = nullptr;
@@ -1194,6 +1287,13 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             const bool host_stop = done || stopped || (next_j == 0 && L >= U);
             const bool dev_stop = ((const bz::ChainState *)words)->done != 0;
             if (host_stop != dev_stop) return fail(BZ_EDEVICE, "internal: device and host bookkeeping disagree");
+            if (dev_recover && dev_stop && best_here && status == BZ_OK) {
+                // the window recovered the witness of the same winning tile
+                const unsigned long long *back = (const unsigned long long *)(stage + kStageRecoverOff);
+                if ((uint32_t)back[0] != 1u) return fail(BZ_EDEVICE, "internal: witness not found in its tile");
+                for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = back[1 + w];
+                witness_done = true;
+            }
         }
     }
     res->lower_bound = L;
@@ -1202,7 +1302,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         status = BZ_ELIMIT;
         g_err = "stats buffer too small";
     }
-    if (status == BZ_OK && want_witness && !finished_in_one) {
+    if (status == BZ_OK && want_witness && !finished_in_one && !witness_done) {
         if (!best.have) return fail(BZ_EDEVICE, "internal: no witness tile");
         bz::RecoverArgs ra{};
         const uint32_t j = best.j;

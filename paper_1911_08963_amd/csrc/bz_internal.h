@@ -133,6 +133,7 @@ struct bz_code {
     size_t dev_one_off = 0;
     size_t one_lds = 0;                 // LDS bytes of the launch
     bool one_lds_binom = false;         // binomials staged in LDS
+    bool one_likely = false;            // the one launch's levels may well end the search
     double prepare_s = 0.0;
     uint32_t W(uint32_t j) const { return j < num_full ? W_full : W_partial; }
     uint32_t k_low(uint32_t j) const { return j < num_full ? k : partial_rank; }

@@ -74,6 +74,34 @@ struct RecoverArgs {
     const uint32_t *pre_rows;    // their indices (device)
 };
 
+// One task of a window, as the window's witness recovery needs it.
+struct RecoverTask {
+    const uint32_t *rows;        // packed rows of the task's Gamma_j
+    const uint64_t *full_rows;   // k x kHostWords full rows of Gamma_j
+    const Rect *rects;           // the task's tiling (device)
+    uint32_t nrects, slots, heads_per_tile, W;
+    uint32_t k_low, _pad;
+};
+static_assert(sizeof(RecoverTask) == 48, "RecoverTask is 48 bytes");
+
+// Witness recovery at the end of a window, before the host has read it back:
+// when the window stopped the search and the winning tile is one of its
+// tasks', the window's last launch recovers the witness on the device.
+struct RecoverWindowArgs {
+    const ChainState *state;             // the window's bounds after its last step
+    const unsigned long long *records;   // the window's records, kRecWords words apart
+    const RecoverTask *tasks;            // ntasks entries
+    const uint64_t *binom;
+    unsigned int *flag;                  // 0 before the launch
+    uint32_t *indices;
+    uint32_t *indices_len;
+    unsigned long long *codeword;        // kHostWords words
+    uint32_t ntasks;
+    uint32_t U0;                         // the upper bound when the window started
+    uint32_t have0;                      // a winning tile was known when the window started
+    uint32_t _pad;
+};
+
 // ---- batched persistent search (bz_min_distance_batch)
 
 // Tiling of level g for one k: rects[rect_off .. rect_off + nrects).
@@ -295,6 +323,9 @@ hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
 hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState *state, const ChainState &init,
                              unsigned int *clear, hipStream_t st);
 hipError_t launch_recover(const RecoverArgs &a, hipStream_t st);
+// threads: the largest tile (combinations) of the window's tasks; the launch
+// takes at most 2048 work-groups of 256 and walks larger tiles in strides.
+hipError_t launch_recover_window(const RecoverWindowArgs &a, uint64_t threads, hipStream_t st);
 
 // ---- the paper's prefix-task schedules (bz_sched.hip, bz_sched.h)
 

@@ -174,11 +174,10 @@ __global__ void bz_chain_init_kernel(unsigned long long *records, uint32_t n, Ch
 // to the rows of the tile's prefix task when it has one. The first thread
 // whose combination has the target weight writes its row indices and the
 // codeword (XOR of the full rows, original coordinates).
-__global__ void bz_recover_kernel(RecoverArgs a) {
+__device__ void recover_tile(const RecoverArgs &a, uint64_t id) {
     const Rect R = a.rect;
     // the tile's lane subsets: lane_mult blocks of 64 * slots
     const uint64_t lane_items = (uint64_t)kWaveSize * a.slots * (R.lane_mult ? R.lane_mult : 1u);
-    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t local = a.tile - R.tile_begin;
     const uint64_t lb = local / R.head_blocks, hb = local - lb * R.head_blocks;
     const uint64_t li = id % lane_items, hs = id / lane_items;
@@ -225,6 +224,62 @@ __global__ void bz_recover_kernel(RecoverArgs a) {
     for (int w = 0; w < kHostWords; ++w) a.codeword[w] = cw[w];
     for (uint32_t i = 0; i < cnt; ++i) a.indices[i] = idx[i];
     a.indices_len[0] = cnt;
+}
+
+__global__ void bz_recover_kernel(RecoverArgs a) {
+    recover_tile(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The window's winning task, by the host's rule (the first task whose minimum
+// reaches the final upper bound), then the same per-thread recovery over its
+// tile. Nothing happens unless the window stopped the search and the winner
+// is one of its tasks: then the host recovers the witness itself.
+__global__ void bz_recover_window_kernel(RecoverWindowArgs a) {
+    if (!a.state->done) return;
+    uint32_t U = a.U0;
+    bool have = a.have0 != 0;
+    int best = -1;
+    uint64_t tile = 0;
+    for (uint32_t i = 0; i < a.ntasks; ++i) {
+        const unsigned long long key = a.records[(size_t)i * kRecWords + kRecKey];
+        const uint32_t tmin = key == ~0ull ? 0xffffffffu : (uint32_t)(key >> kTileBits);
+        if (tmin < U || (tmin == U && !have)) {
+            U = tmin;
+            have = true;
+            best = (int)i;
+            tile = key & kTileMask;
+        }
+    }
+    if (best < 0) return;
+    const RecoverTask T = a.tasks[best];
+    uint32_t lo = 0, hi = T.nrects - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (T.rects[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    RecoverArgs r{};
+    r.rows = T.rows;
+    r.full_rows = T.full_rows;
+    r.binom = a.binom;
+    r.rect = T.rects[lo];
+    r.flag = a.flag;
+    r.indices = a.indices;
+    r.indices_len = a.indices_len;
+    r.codeword = a.codeword;
+    r.tile = tile;
+    r.slots = T.slots;
+    r.heads_per_tile = T.heads_per_tile;
+    r.W = T.W;
+    r.k_low = T.k_low;
+    r.target = U;
+    r.pre_n = 0;
+    // a grid-stride walk over the tile's combinations, left once one is found
+    const uint64_t n = (uint64_t)kWaveSize * T.slots * (r.rect.lane_mult ? r.rect.lane_mult : 1u) * T.heads_per_tile;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += stride) {
+        recover_tile(r, id);
+        if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -291,6 +346,12 @@ hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState
                              unsigned int *clear, hipStream_t st) {
     if (n > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(bz_chain_init_kernel, dim3(1), dim3(64), 0, st, records, n, state, init, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_recover_window(const RecoverWindowArgs &a, uint64_t threads, hipStream_t st) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((threads + 255) / 256, 2048);
+    hipLaunchKernelGGL(bz_recover_window_kernel, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -64,6 +64,17 @@ def _compare(bz, G, n, *, level_stop=False, slots=0, heads=0, max_level=0, tag="
     assert got.launches == len(ref.stats)
     if got.status == 0:
         _check_witness(got, G, n)
+    # one launch per task on every level (the smallest levels otherwise may run
+    # in one single-work-group launch): the same search
+    per_task = bz.min_distance(code, stats=True, level_stop=level_stop, slots_per_lane=slots,
+                               heads_per_tile=heads, max_level=max_level, raise_on_error=False,
+                               task_launches=True)
+    assert (per_task.status, per_task.d, per_task.lower_bound, per_task.upper_bound) == \
+        (got.status, got.d, got.lower_bound, got.upper_bound)
+    assert [tuple(s) for s in per_task.stats] == [tuple(s) for s in got.stats]
+    assert per_task.combinations == got.combinations
+    if per_task.status == 0:
+        _check_witness(per_task, G, n)
     fast = bz.min_distance(code, level_stop=level_stop, slots_per_lane=slots, heads_per_tile=heads,
                            max_level=max_level, raise_on_error=False)
     assert fast.status == ref.status and fast.d == ref.d
