@@ -305,7 +305,9 @@ def serving_runs(args, pool, nprocs) -> dict:
         say(f"serving cpu baseline: {cpu['codes']} codes, {cpu['comb_per_s']:.3e} comb/s on {nprocs} cores")
     if args.serve_variants_seconds > 0:
         sv["variants"] = {}
-        for name, kw in (("hbm_budget_binding", {"hbm_budget": 256 * 1024}),
+        # a request of this stream needs at most about 16 KiB of device memory (Gamma_j rows and
+        # their prefix XORs, full rows, code state, task records): 32 KiB admits two at a time
+        for name, kw in (("hbm_budget_binding", {"hbm_budget": 32 * 1024}),
                          ("codes_per_launch_256", {"codes_per_launch": 256})):
             v = serving.run(args.serve_rate, args.serve_variants_seconds, cost_cap=args.serve_cap,
                             progress=say, **kw)

@@ -229,6 +229,7 @@ bz_status batch_layout(bz_code *const *codes, uint32_t count, const bz_opts &opt
         const bz_code *c = codes[i];
         bz::BatchCode d{};
         d.rows = (const uint32_t *)c->dev;
+        d.px_delta = c->px_delta;
         d.full_rows = (const uint64_t *)((const char *)c->dev + c->dev_full_off);
         d.n = c->n; d.k = c->k; d.m_f = c->num_full; d.k_m = c->partial_rank;
         d.nsets = c->nsets; d.W_full = c->W_full; d.W_partial = c->W_partial;
@@ -593,8 +594,10 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
     } else {
         BZ_HIP(hipGetDevice(&c->device));
     }
-    // device layout: per matrix (k + 1) x W dwords (the last row zero), then
-    // the full rows at a 256-byte boundary
+    // device layout: per matrix (k + 1) x W dwords (the last row zero); then
+    // the same again holding prefix XORs (entry i of matrix j: the XOR of its
+    // rows 0..i-1, for the lane setup's successor steps); then the full rows
+    // at a 256-byte boundary
     std::vector<uint32_t> dev_packed;
     std::vector<size_t> dev_off;
     for (uint32_t j = 0; j < c->nsets; ++j) {
@@ -603,6 +606,16 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
         dev_packed.insert(dev_packed.end(), c->packed.begin() + c->packed_off[j],
                           c->packed.begin() + c->packed_off[j] + (size_t)k * W);
         dev_packed.insert(dev_packed.end(), W, 0u);
+    }
+    c->px_delta = (uint32_t)dev_packed.size();
+    for (uint32_t j = 0; j < c->nsets; ++j) {
+        const uint32_t W = c->W(j);
+        const size_t base = dev_packed.size();
+        dev_packed.insert(dev_packed.end(), (size_t)(k + 1) * W, 0u);
+        for (uint32_t i = 0; i < k; ++i)
+            for (uint32_t w = 0; w < W; ++w)
+                dev_packed[base + (size_t)(i + 1) * W + w] =
+                    dev_packed[base + (size_t)i * W + w] ^ dev_packed[dev_off[j] + (size_t)i * W + w];
     }
     c->packed_off = dev_off;
     c->packed = dev_packed;
@@ -656,6 +669,7 @@ bz_status bz_prepare(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld_word
         oa.k = k; oa.k_m = c->partial_rank; oa.m_f = c->num_full;
         oa.U0 = n - k + 1;
         oa.row_words = (uint32_t)dev_packed.size();
+        oa.px_delta = c->px_delta;
         const uint32_t glast = c->one_tasks.back().g;
         c->one_lds = ((size_t)oa.row_words * 4 + 7) & ~(size_t)7;
         if (bz::batch_lds_bytes(k, glast) <= 32 * 1024) {

@@ -72,7 +72,7 @@ __device__ __forceinline__ T ld_agent(const T *p) {
 
 // One tile of a code's current task. The tile's combination count and
 // statistics go to the wave's own words (LDS), which the caller adds to the
-// task's once per claim.
+// task's once per claim. The lane setup steps with the rows' prefix XORs.
 template <bool STATS>
 __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, uint64_t epoch, uint64_t tile,
                                            uint32_t lane, cptr64 binom_c, const uint64_t *sb, uint32_t bt,
@@ -92,6 +92,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     // into SGPRs, as in the single-code kernel, not with vector loads
     const uint32_t *rows =
         (const uint32_t *)uni64((uint64_t)(D.rows + (size_t)(partial ? m_f : j) * (k + 1) * W_full));
+    const uint32_t *px = rows + uni(D.px_delta);       // the rows' prefix XORs
     TaskArgs a{};
     a.rows = rows;
     a.binom = b.binom;
@@ -117,10 +118,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &b, uint32_t code, ui
     switch (W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
     case WW * 2:                                                                                      \
-        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, nullptr, sb, bt, rp, tile, lane); \
+        run_tile<WW, slots_for_w(WW), false, STATS>(a, rc, binom_c, rows, px, sb, bt, rp, tile, lane);      \
         break;                                                                                        \
     case WW * 2 + 1:                                                                                  \
-        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, nullptr, sb, bt, rp, tile, lane);  \
+        run_tile<WW, slots_for_w(WW), true, STATS>(a, rc, binom_c, rows, px, sb, bt, rp, tile, lane);       \
         break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
@@ -354,13 +355,14 @@ __device__ __forceinline__ void one_tile(const OneArgs &a, const OneTask &T, uin
     cptr32 rc = (cptr32)rows;
     cptr_rect rp = (cptr_rect)t.rects;
     const uint32_t *srow = lrows + T.row_off;
+    const uint32_t *spx = srow + a.px_delta;
     switch (T.W * 2 + (partial ? 1u : 0u)) {
 #define BZ_CASE(WW)                                                                                   \
     case WW * 2:                                                                                      \
-        run_tile<WW, slots_for_w(WW), false, STATS>(t, rc, binom_c, srow, nullptr, sb, bt, rp, tile, lane); \
+        run_tile<WW, slots_for_w(WW), false, STATS>(t, rc, binom_c, srow, spx, sb, bt, rp, tile, lane);     \
         break;                                                                                        \
     case WW * 2 + 1:                                                                                  \
-        run_tile<WW, slots_for_w(WW), true, STATS>(t, rc, binom_c, srow, nullptr, sb, bt, rp, tile, lane);  \
+        run_tile<WW, slots_for_w(WW), true, STATS>(t, rc, binom_c, srow, spx, sb, bt, rp, tile, lane);      \
         break;
         BZ_CASE(1) BZ_CASE(2) BZ_CASE(3) BZ_CASE(4) BZ_CASE(5) BZ_CASE(6) BZ_CASE(7) BZ_CASE(8)
 #undef BZ_CASE
@@ -896,8 +898,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     queue_loop<STATS, false, LDS_BINOM>(*b, nullptr);
 }
 
+// Three waves per SIMD: left to itself the compiler gives the fast variant 222
+// VGPRs (two waves) once the lane setup steps with prefix XORs; capped it fits
+// in 167 with no more spill than before.
 template <bool STATS>
-__global__ __launch_bounds__(kBlock) void bz_serve_kernel(const ServeArgs *__restrict__ sv) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bz_serve_kernel(
+    const ServeArgs *__restrict__ sv) {
     queue_loop<STATS, true, false>(sv->b, sv);
 }
 

@@ -125,6 +125,7 @@ struct bz_code {
     void *dev = nullptr;                // device copy: packed rows, then full rows
     size_t dev_bytes = 0;
     size_t dev_full_off = 0;            // byte offset of the full rows in dev
+    uint32_t px_delta = 0;              // dwords from packed rows to their prefix XORs in packed
     // the smallest levels' one launch: task list, the tiling of each task's
     // level (one_plan_of), and where its arguments, tasks and rectangles sit in dev
     std::vector<bz::OneTask> one_tasks;

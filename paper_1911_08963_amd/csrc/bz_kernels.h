@@ -123,7 +123,8 @@ struct alignas(64) BatchCode {
     uint32_t stats_off, stats_cap;
     uint32_t flags, max_level;   // BZ_F_LEVEL_STOP; stop after this level (0 = no limit)
     uint64_t tag;                // serving: the request's ticket
-    uint32_t slot, _pad;         // serving: the completion record and statistics slot
+    uint32_t slot;               // serving: the completion record and statistics slot
+    uint32_t px_delta;           // dwords from rows to the rows' prefix XORs (same layout per matrix)
 };
 static_assert(sizeof(BatchCode) % 64 == 0, "BatchCode fills whole cache lines");
 
@@ -228,8 +229,8 @@ struct OneArgs {
     uint32_t ntasks, k, k_m, m_f;
     uint32_t U0;                  // n - k + 1
     uint32_t lds_g;               // binomials C(x, y), y <= lds_g, staged in LDS (0: read from binom)
-    uint32_t row_words;           // packed-row dwords of all matrices, staged in LDS
-    uint32_t _pad;
+    uint32_t row_words;           // packed-row and prefix-XOR dwords of all matrices, staged in LDS
+    uint32_t px_delta;            // dwords from a matrix's rows to its prefix XORs
 };
 
 // Arguments of one search (by value).

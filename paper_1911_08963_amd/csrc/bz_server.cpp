@@ -44,7 +44,7 @@ constexpr uint32_t kMaxPlans = 4096;            // distinct (k, slots) plans per
 constexpr uint32_t kPlanEntries = 1u << 17;     // PlanEntry table (4 MiB)
 constexpr uint32_t kPlanRects = 1u << 19;       // Rect table (40 MiB)
 constexpr uint64_t kLogCap = 1ull << 20;        // shared task log ring
-constexpr size_t kSlotBytes = 32 * 1024;        // staged payload of one request (n <= 256 needs < 25 KiB)
+constexpr size_t kSlotBytes = 48 * 1024;        // staged payload of one request (n <= 256 needs <= 40 KiB)
 constexpr uint32_t kEntryAlign = 8;             // plans start on 256-byte boundaries ...
 constexpr uint32_t kRectAlign = 16;             // ... in both tables (16 x 80 B = 5 x 256 B)
 // Tiles of a served request: each level is cut into about target_tiles tiles
@@ -476,6 +476,7 @@ bz_status bz_server_submit(bz_server *s, const bz_code *c, const bz_opts *o, bz_
 
     bz::BatchCode &D = R.code;
     D.rows = (const uint32_t *)dst;
+    D.px_delta = c->px_delta;
     D.full_rows = (const uint64_t *)(dst + c->dev_full_off);
     D.n = n; D.k = k; D.m_f = c->num_full; D.k_m = c->partial_rank;
     D.nsets = c->nsets; D.W_full = c->W_full; D.W_partial = c->W_partial; D.g_max = gmax;
