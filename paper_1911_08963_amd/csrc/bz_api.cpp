@@ -71,7 +71,6 @@ using bz::now_s;
 // runs between two host synchronisations; each task has a record of
 // kRecWords words (key, counts and claim counter on separate 128-byte lines),
 // after the window's bounds (bz::ChainState).
-constexpr size_t kWsRecover = 384;     // flag, len (u32), codeword (4 x u64)
 constexpr size_t kWsIndices = 512;     // the witness's row indices: up to 384 u32 before kWsPreRows
 constexpr size_t kWsPreRows = 2048;    // a prefix task's rows, up to 64 u32
 constexpr size_t kWsRecTasks = 2304;   // a window's tasks for its witness recovery (bz::RecoverTask)
@@ -81,6 +80,9 @@ constexpr uint32_t kChainMax = 32;
 constexpr size_t kRecBytes = bz::kRecWords * 8;
 constexpr size_t kWsChain = kWsRects + kMaxRects * sizeof(bz::Rect);   // ChainState, then the records
 constexpr size_t kChainBytes = 128 + kChainMax * kRecBytes;
+// the witness recovery's flag, length (u32) and codeword (4 x u64), in the
+// window state's line: a window's one read-back returns them with its records
+constexpr size_t kWsRecover = kWsChain + 64;
 // Where a one launch of the code's smallest levels writes its state and
 // records when they cannot go straight to pinned host memory.
 constexpr size_t kWsOne = kWsChain + kChainBytes;
@@ -88,7 +90,8 @@ constexpr size_t kOneStatsOff = sizeof(bz::OneState);
 constexpr size_t kOneBytes = kOneStatsOff + bz::kOneMaxTasks * sizeof(bz::BatchStat);
 constexpr size_t kWsBytes = kWsOne + ((kOneBytes + 255) & ~(size_t)255);
 static_assert(sizeof(bz::ChainState) <= 128, "bounds fit their line");
-static_assert(kWsRecover + 8 + bz::kHostWords * sizeof(uint64_t) <= kWsIndices, "flag, length and codeword fit");
+static_assert(sizeof(bz::ChainState) <= 64 && 64 + 8 + bz::kHostWords * sizeof(uint64_t) <= 128,
+              "the window state, then the recovery's flag, length and codeword, fit one line");
 static_assert(kWsPreRows - kWsIndices >= (size_t)bz::kBinomT * sizeof(uint32_t),
               "the recovered combination's row indices (g <= kBinomT) fit below the prefix rows");
 static_assert(kWsRecTasks - kWsPreRows >= 64 * sizeof(uint32_t), "a prefix task's rows fit below the window's tasks");
@@ -120,6 +123,11 @@ std::shared_ptr<const bz::LevelPlan> cached_plan(uint32_t k, uint32_t g, uint32_
     return p;
 }
 
+// Levels of fewer sums than this run their full-rank Gamma_j in one launch
+// (up to bz::kMaxGroup of them): their launches are mostly fixed cost, and the
+// work a task past the stop still does there is small.
+constexpr double kGroupMaxComb = 134217728.0;   // 2^27
+
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
 // later matrices at level g-1 (j == m_f is the partial matrix).
 uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t k) {
@@ -138,10 +146,8 @@ uint32_t certified(uint32_t j, uint32_t g, uint32_t m_f, uint32_t k_m, uint32_t 
 // the process ends.
 constexpr size_t kStageBytes = 64 * 1024;
 constexpr size_t kPinnedBytes = kChainBytes + kStageBytes;
-// the staging area's tail: a window's tasks for the recovery, and before them
-// the recovery's read-back (flag and length, codeword)
+// the staging area's tail: a window's tasks for the recovery
 constexpr size_t kStageTasksOff = kStageBytes - kChainMax * sizeof(bz::RecoverTask);
-constexpr size_t kStageRecoverOff = kStageTasksOff - 64;
 static_assert(kOneBytes <= kChainBytes, "a one launch's state and records fit the read-back buffer");
 class PinnedWords {
   public:
@@ -1098,7 +1104,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         if (!staged.empty()) {
             const size_t off = placed.front().second, bytes = staged.size() * sizeof(bz::Rect);
             const void *src = staged.data();
-            if (bytes <= kStageRecoverOff) {            // the previous window's copies have finished
+            if (bytes <= kStageTasksOff) {              // the previous window's copies have finished
                 std::memcpy(stage, staged.data(), bytes);
                 src = stage;
             }
@@ -1110,18 +1116,46 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         init.exit_at = stats ? 0u : Lcert;
         init.L = L;
         init.Lcert = Lcert;
-        BZ_HIP(bz::launch_chain_init(d_records, (uint32_t)win.size(), d_state, init,
-                                     want_witness ? (unsigned int *)(ws + kWsRecover) : nullptr, st));
         // an enumeration window recovers its witness on the device when it
         // ends the search: no further synchronisation after the read-back
         const bool dev_recover = want_witness && !use_sched;
-        auto *rtasks = (bz::RecoverTask *)(stage + kStageTasksOff);
         uint64_t rec_threads = 0;
+        if (dev_recover) {
+            auto *rtasks = (bz::RecoverTask *)(stage + kStageTasksOff);
+            for (size_t i = 0; i < win.size(); ++i) {
+                const Task &t = win[i];
+                bz::RecoverTask &rt = rtasks[i];
+                rt = bz::RecoverTask{};
+                rt.rows = (const uint32_t *)c->dev + c->packed_off[t.j];
+                rt.full_rows = (const uint64_t *)((char *)c->dev + c->dev_full_off) + (size_t)t.j * k * bz::kHostWords;
+                rt.rects = d_rects + on_device.at(t.key);
+                rt.nrects = (uint32_t)t.plan->rects.size();
+                rt.slots = t.slots;
+                rt.heads_per_tile = t.plan->heads_per_tile;
+                rt.W = t.W;
+                rt.k_low = c->k_low(t.j);
+                uint32_t mult = 1;
+                for (const bz::Rect &r : t.plan->rects) mult = std::max(mult, r.lane_mult);
+                rec_threads = std::max<uint64_t>(rec_threads,
+                                                 (uint64_t)bz::kWaveSize * t.slots * mult * t.plan->heads_per_tile);
+            }
+            BZ_HIP(hipMemcpyAsync(ws + kWsRecTasks, rtasks, win.size() * sizeof(bz::RecoverTask),
+                                  hipMemcpyHostToDevice, st));
+        }
+        BZ_HIP(bz::launch_chain_init(d_records, (uint32_t)win.size(), d_state, init,
+                                     want_witness ? (unsigned int *)(ws + kWsRecover) : nullptr, st));
         const uint32_t U_start = U;
         const bool have_start = best.have;
         for (size_t i = 0; i < win.size(); ++i) {
             const Task &t = win[i];
             unsigned long long *rec = d_records + i * bz::kRecWords;
+            // consecutive full-rank tasks of a small level share one launch
+            uint32_t group = 1;
+            if (!t.sp && t.j < m_f && (double)bz::binom_sat(k, t.g) < kGroupMaxComb)
+                while (group < bz::kMaxGroup && i + group < win.size() && !win[i + group].sp &&
+                       win[i + group].g == t.g && win[i + group].j == t.j + group && win[i + group].j < m_f &&
+                       win[i + group].key == t.key && bz::enum_lds_bytes(k, t.g, t.W, group + 1) <= 65536)
+                    ++group;
             bz::TaskArgs a{};
             a.rows = (const uint32_t *)c->dev + c->packed_off[t.j];
             a.binom = dc.binom;
@@ -1166,7 +1200,13 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                 a.nrects = (uint32_t)t.plan->rects.size();
                 a.heads_per_tile = t.plan->heads_per_tile;
                 a.total_tiles = t.plan->total_tiles;
-                const uint64_t blocks = (t.plan->total_tiles + 3) / 4;
+                a.group = group;
+                a.rows_stride = group > 1 ? (uint32_t)(c->packed_off[t.j + 1] - c->packed_off[t.j]) : 0u;
+                for (uint32_t q = 0; q < group; ++q) {
+                    a.cert_tasks[q] = certified(t.j + q, t.g, m_f, k_m, k);
+                    if (t.j + q == last_j) a.last_mask |= 1u << q;
+                }
+                const uint64_t blocks = (group * t.plan->total_tiles + 3) / 4;
                 const uint32_t grid =
                     (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)dc.cus * 8));
                 // the task's bookkeeping step runs in its last work-group
@@ -1180,30 +1220,13 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                 cs.cert_level = level_bound(t.g);
                 cs.level_stop = level_stop;
                 cs.stats = stats;
-                if (dev_recover) {
-                    bz::RecoverTask &rt = rtasks[i];
-                    rt = bz::RecoverTask{};
-                    rt.rows = a.rows;
-                    rt.full_rows = (const uint64_t *)((char *)c->dev + c->dev_full_off) + (size_t)t.j * k * bz::kHostWords;
-                    rt.rects = a.rects;
-                    rt.nrects = a.nrects;
-                    rt.slots = t.slots;
-                    rt.heads_per_tile = a.heads_per_tile;
-                    rt.W = t.W;
-                    rt.k_low = a.k_low;
-                    uint32_t mult = 1;
-                    for (const bz::Rect &r : t.plan->rects) mult = std::max(mult, r.lane_mult);
-                    rec_threads = std::max<uint64_t>(rec_threads,
-                                                     (uint64_t)bz::kWaveSize * t.slots * mult * a.heads_per_tile);
-                }
                 if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
                 BZ_HIP(bz::launch_enum(a, t.W, t.slots, t.j >= m_f, stats, grid, st));
+                i += group - 1;
             }
         }
         if (ev1) BZ_HIP(hipEventRecord(ev1, st));
         if (dev_recover) {
-            BZ_HIP(hipMemcpyAsync(ws + kWsRecTasks, rtasks, win.size() * sizeof(bz::RecoverTask),
-                                  hipMemcpyHostToDevice, st));
             bz::RecoverWindowArgs ra{};
             ra.state = d_state;
             ra.records = d_records;
@@ -1219,9 +1242,6 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             BZ_HIP(bz::launch_recover_window(ra, rec_threads, st));
         }
         BZ_HIP(hipMemcpyAsync(words, ws + kWsChain, 128 + win.size() * kRecBytes, hipMemcpyDeviceToHost, st));
-        if (dev_recover)
-            BZ_HIP(hipMemcpyAsync(stage + kStageRecoverOff, ws + kWsRecover, (1 + bz::kHostWords) * sizeof(uint64_t),
-                                  hipMemcpyDeviceToHost, st));
         BZ_HIP(hipStreamSynchronize(st));
         if (ev0) {
             float ms = 0.f;
@@ -1303,7 +1323,7 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             if (host_stop != dev_stop) return fail(BZ_EDEVICE, "internal: device and host bookkeeping disagree");
             if (dev_recover && dev_stop && best_here && status == BZ_OK) {
                 // the window recovered the witness of the same winning tile
-                const unsigned long long *back = (const unsigned long long *)(stage + kStageRecoverOff);
+                const unsigned long long *back = words + (kWsRecover - kWsChain) / 8;
                 if ((uint32_t)back[0] != 1u) return fail(BZ_EDEVICE, "internal: witness not found in its tile");
                 for (uint32_t w = 0; w < (n + 63) / 64; ++w) res->witness[w] = back[1 + w];
                 witness_done = true;

@@ -401,9 +401,19 @@ __device__ bool one_witness(const OneArgs &a, const OneTask &T, uint64_t tile, u
     default: break;
     }
     if (!found) return false;
+    // the digits from the binomials in LDS (row stride bt), the rows from memory
     const uint64_t *full = a.full_rows + (size_t)T.j * a.k * kHostWords;
-    unrank_xor(a.binom, q, g.lane_t, g.lane_off, g.lane_n, full, cw);
-    if (g.head_t) unrank_xor(a.binom, h, g.head_t, g.head_off, g.head_n, full, cw);
+    auto xor_subset = [&](uint64_t r, uint32_t t, uint32_t off, uint32_t nside) {
+        uint32_t hi = nside - 1;
+        for (uint32_t i = t; i >= 1; --i) {
+            const uint32_t c = colex_digit(sb, bt, i, i - 1, hi, r);
+            r -= sb[c * bt + i];
+            for (int w = 0; w < kHostWords; ++w) cw[w] ^= full[(size_t)(off + c) * kHostWords + w];
+            hi = c - 1;
+        }
+    };
+    xor_subset(q, g.lane_t, g.lane_off, g.lane_n);
+    if (g.head_t) xor_subset(h, g.head_t, g.head_off, g.head_n);
     return true;
 }
 

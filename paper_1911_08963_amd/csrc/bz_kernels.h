@@ -25,6 +25,9 @@ struct ChainState {
 constexpr uint32_t kRecWords = 48;       // 384 bytes
 constexpr uint32_t kRecKey = 0, kRecStats = 16, kRecNcomb = 17, kRecCtr = 32;
 
+// Tasks of one level that may share a launch (TaskArgs::group).
+constexpr uint32_t kMaxGroup = 4;
+
 // One task's step of the device-side bookkeeping (run after the task).
 struct ChainStep {
     ChainState *state;
@@ -57,6 +60,15 @@ struct TaskArgs {
     const ChainState *chain;     // when set: u_prev and exit_at come from here, and a stopped search skips the task
     ChainStep step;              // when step.state is set: the last work-group to leave applies the task's
                                  // bookkeeping step (counting the work-groups in tile_ctr, zero at the start)
+    // A group of consecutive tasks of one level in one launch (enumeration
+    // kernel only): Gamma_j .. Gamma_j+group-1, all full rank, same tiling.
+    // Task i's rows are at rows + i * rows_stride, its record kRecWords words
+    // after task i-1's (key, stats, ncomb, tile_ctr), its step is step with
+    // cert_task = cert_tasks[i] and last_of_level = bit i of last_mask.
+    uint32_t group;              // 0 or 1: one task
+    uint32_t rows_stride;
+    uint32_t cert_tasks[kMaxGroup];
+    uint32_t last_mask;
 };
 
 struct RecoverArgs {
@@ -316,7 +328,7 @@ constexpr size_t kBatchLdsMax = 24 * 1024;
 
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st);
-size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W);
+size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W, uint32_t group = 1);
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
 // Resets n task records (kRecWords each), writes the window's starting bounds

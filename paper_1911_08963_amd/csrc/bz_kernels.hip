@@ -53,21 +53,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
         exit_at = a.chain->exit_at;
     }
     extern __shared__ uint64_t smem[];
+    const uint32_t G = a.group > 1 ? a.group : 1u;       // tasks of this launch
     const uint32_t bt = a.g + 1;                          // binomial row stride in LDS
     uint64_t *sbin = smem;                                // (k+1) x (g+1)
-    uint32_t *srow = (uint32_t *)(smem + (size_t)(a.k + 1) * bt);   // k x W
+    uint32_t *srows = (uint32_t *)(smem + (size_t)(a.k + 1) * bt);   // G x k x W
+    uint32_t *spxs = srows + (size_t)G * a.k * W;         // G x (k+1) x W prefix XORs
     for (uint32_t i = threadIdx.x; i < (a.k + 1) * bt; i += blockDim.x) {
         uint32_t x = i / bt, y = i - x * bt;
         sbin[i] = a.binom[x * (kBinomT + 1) + y];
     }
-    for (uint32_t i = threadIdx.x; i < a.k * W; i += blockDim.x) srow[i] = a.rows[i];
-    uint32_t *spx = srow + a.k * W;                      // (k+1) x W prefix XORs
+    for (uint32_t i = threadIdx.x; i < G * a.k * W; i += blockDim.x) {
+        const uint32_t ti = i / (a.k * W), r = i - ti * (a.k * W);
+        srows[i] = a.rows[(size_t)ti * a.rows_stride + r];
+    }
     __syncthreads();
-    build_prefix_xor<W>(srow, spx, a.k);
+    for (uint32_t ti = 0; ti < G; ++ti) build_prefix_xor<W>(srows + ti * a.k * W, spxs + ti * (a.k + 1) * W, a.k);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & (kWaveSize - 1);
-    cptr32 rows = (cptr32)a.rows;
     cptr_rect rect_p = (cptr_rect)a.rects;
     cptr64 binom_c = (cptr64)a.binom;
     // Static round-robin of tiles over waves: the tile index is uniform
@@ -79,29 +82,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
     // The wave's combination count and statistics word live in LDS until it
     // leaves: one global atomic per wave instead of one per tile on the same
     // word (on a level of many short tiles those serialise the whole launch).
-    __shared__ unsigned long long wave_words[kBlock / kWaveSize][2];
+    __shared__ unsigned long long wave_words[kBlock / kWaveSize][kMaxGroup][2];
     const uint32_t wv = uni(threadIdx.x / kWaveSize);
-    if (lane == 0) {
-        wave_words[wv][0] = 0;
-        wave_words[wv][1] = ~0ull;                       // "none", as the task's own word starts
-    }
-    TaskArgs t = a;
-    t.ncomb = &wave_words[wv][0];
-    t.stats = &wave_words[wv][1];
-    for (uint64_t it = first; it < a.total_tiles; it += stride) {
-        const uint64_t tile = uni64(it);
-        bool stop = false;
-        if (exit_at) {
-            unsigned long long kv = __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t cur = min((uint32_t)(kv >> kTileBits), u_prev);
-            stop = uni(cur) <= exit_at;
+    if (lane == 0)
+        for (uint32_t ti = 0; ti < kMaxGroup; ++ti) {
+            wave_words[wv][ti][0] = 0;
+            wave_words[wv][ti][1] = ~0ull;               // "none", as the task's own word starts
         }
+    TaskArgs t = a;
+    for (uint64_t it = first; it < G * a.total_tiles; it += stride) {
+        // tile of task ti (all tasks of a group share the tiling)
+        const uint32_t ti = uni((uint32_t)(it / a.total_tiles));
+        const uint64_t tile = uni64(it - (uint64_t)ti * a.total_tiles);
         if (a.cancel) {
             uint32_t cv = __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            stop = stop || uni(cv) != 0u;
+            if (uni(cv) != 0u) break;
         }
-        if (stop) break;
-        run_tile<W, SLOTS, PARTIAL, STATS>(t, rows, binom_c, srow, spx, sbin, bt, rect_p, tile, lane);
+        t.rows = a.rows + (size_t)ti * a.rows_stride;
+        t.key = a.key + (size_t)ti * kRecWords;
+        t.ncomb = &wave_words[wv][ti][0];
+        t.stats = &wave_words[wv][ti][1];
+        if (exit_at) {
+            // the task's own minimum and the bound from before the launch: a
+            // later task of the group may not cut an earlier one short
+            unsigned long long kv = __hip_atomic_load(t.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t cur = min((uint32_t)(kv >> kTileBits), u_prev);
+            if (uni(cur) <= exit_at) continue;
+        }
+        cptr32 rows = (cptr32)uni64((uint64_t)t.rows);
+        run_tile<W, SLOTS, PARTIAL, STATS>(t, rows, binom_c, srows + ti * a.k * W, spxs + ti * (a.k + 1) * W, sbin,
+                                           bt, rect_p, tile, lane);
     }
     // One global atomic per work-group, not per wave: when the waves of a
     // short level end together, atomics on the same word queue up at the
@@ -109,33 +119,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
     // 12-19 us there).
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long nc = 0;
-        uint32_t smin = 0xffffffffu;
-        uint64_t scnt = 0;
-        for (uint32_t w = 0; w < kBlock / kWaveSize; ++w) {
-            nc += wave_words[w][0];
-            const unsigned long long sw = wave_words[w][1];
-            if (STATS && wave_words[w][0] && sw != ~0ull) {
-                const uint32_t m = (uint32_t)(sw >> kCountBits);
-                if (m < smin) { smin = m; scnt = sw & kCountMask; }
-                else if (m == smin) scnt += sw & kCountMask;
+        for (uint32_t ti = 0; ti < G; ++ti) {
+            unsigned long long nc = 0;
+            uint32_t smin = 0xffffffffu;
+            uint64_t scnt = 0;
+            for (uint32_t w = 0; w < kBlock / kWaveSize; ++w) {
+                nc += wave_words[w][ti][0];
+                const unsigned long long sw = wave_words[w][ti][1];
+                if (STATS && wave_words[w][ti][0] && sw != ~0ull) {
+                    const uint32_t m = (uint32_t)(sw >> kCountBits);
+                    if (m < smin) { smin = m; scnt = sw & kCountMask; }
+                    else if (m == smin) scnt += sw & kCountMask;
+                }
+            }
+            if (nc) {
+                atomicAdd(a.ncomb + (size_t)ti * kRecWords, nc);
+                if (STATS && smin != 0xffffffffu) stats_merge(a.stats + (size_t)ti * kRecWords, smin, scnt);
             }
         }
-        if (nc) {
-            atomicAdd(a.ncomb, nc);
-            if (STATS && smin != 0xffffffffu) stats_merge(a.stats, smin, scnt);
-        }
         if (a.step.state) {
-            // the last work-group to leave applies the task's bookkeeping step,
-            // in place of a launch of its own: every other work-group's
-            // atomics are ordered before its count (release), and read after
-            // the last count (acquire)
+            // the last work-group to leave applies the tasks' bookkeeping
+            // steps, in Alg. 1's order, in place of launches of their own:
+            // every other work-group's atomics are ordered before its count
+            // (release), and read after the last count (acquire)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned long long left = atomicAdd(a.tile_ctr, 1ull);
             if (left + 1 == gridDim.x) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                chain_step_apply(a.step, __hip_atomic_load(a.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                 __hip_atomic_load(a.ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                for (uint32_t ti = 0; ti < G; ++ti) {
+                    ChainStep s = a.step;
+                    s.key = a.key + (size_t)ti * kRecWords;
+                    s.ncomb = a.ncomb + (size_t)ti * kRecWords;
+                    if (G > 1) {
+                        s.cert_task = a.cert_tasks[ti];
+                        s.last_of_level = (a.last_mask >> ti) & 1u;
+                    }
+                    chain_step_apply(s, __hip_atomic_load(s.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                     __hip_atomic_load(s.ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                }
             }
         }
     }
@@ -317,7 +338,7 @@ static hipError_t launch_w(const TaskArgs &a, uint32_t slots, bool partial, bool
 
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st) {
-    const size_t lds = enum_lds_bytes(a.k, a.g, W);
+    const size_t lds = enum_lds_bytes(a.k, a.g, W, a.group);
     switch (W) {
     case 1: return launch_w<1>(a, slots, partial, stats, grid, lds, st);
     case 2: return launch_w<2>(a, slots, partial, stats, grid, lds, st);
@@ -331,9 +352,10 @@ hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool parti
     }
 }
 
-size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W) {
-    // binomials, rows, prefix XORs of the rows
-    return (size_t)(k + 1) * (g + 1) * sizeof(uint64_t) + (size_t)(2 * k + 1) * W * sizeof(uint32_t);
+size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W, uint32_t group) {
+    // binomials, then per task of the group its rows and their prefix XORs
+    return (size_t)(k + 1) * (g + 1) * sizeof(uint64_t) +
+           (size_t)(group > 1 ? group : 1) * (2 * k + 1) * W * sizeof(uint32_t);
 }
 
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats, unsigned long long *ncomb,

@@ -57,8 +57,9 @@ struct XorBasis {
     }
 };
 
-// Reduced echelon form of rows under a column order. Returns the rank.
-uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order) {
+// Reduced echelon form of rows under a column order (rows of nw words).
+// Returns the rank.
+uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order, uint32_t nw) {
     uint32_t k = (uint32_t)rows.size(), r = 0;
     for (uint32_t c : order) {
         if (r == k) break;
@@ -68,7 +69,7 @@ uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order) 
         std::swap(rows[p], rows[r]);
         for (uint32_t i = 0; i < k; ++i) {
             if (i == r || !bit(rows[i], c)) continue;
-            for (int w = 0; w < kHostWords; ++w) rows[i][w] ^= rows[r][w];
+            for (uint32_t w = 0; w < nw; ++w) rows[i][w] ^= rows[r][w];
         }
         ++r;
     }
@@ -144,11 +145,12 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
     if (opts && opts->perm_trials > 100000) { err = "perm_trials above 100000"; return BZ_EINVAL; }
     if (opts && (opts->flags & ~(uint32_t)BZ_PREPARE_HOST_ONLY)) { err = "unknown prepare flag"; return BZ_EINVAL; }
 
+    const uint32_t nw = (n + 63) / 64;
     std::vector<HostRow> rows(k);
     for (uint32_t i = 0; i < k; ++i) {
         rows[i].fill(0);
-        for (uint32_t w = 0; w < (n + 63) / 64; ++w) rows[i][w] = G[(size_t)i * ld + w];
-        for (uint32_t cc = n; cc < (uint32_t)kMaxN; ++cc) rows[i][cc >> 6] &= ~(1ull << (cc & 63));
+        for (uint32_t w = 0; w < nw; ++w) rows[i][w] = G[(size_t)i * ld + w];
+        if (n & 63) rows[i][nw - 1] &= (1ull << (n & 63)) - 1;      // bits past column n - 1
     }
     // columns as k-bit vectors
     std::vector<ColVec> col(n);
@@ -184,23 +186,22 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
         std::vector<uint32_t> order(S.begin(), S.end());
         for (uint32_t cc = 0; cc < n; ++cc) if (!in[cc]) order.push_back(cc);
         std::vector<HostRow> gam = rows;
-        uint32_t rk = reduce(gam, order);
+        uint32_t rk = reduce(gam, order, nw);
         if (rk != k) { err = "internal: Gamma_j lost rank"; return BZ_ERANK; }
         // the identity part on S (rows 0..|S|-1) is implied by the pivot order
         for (uint32_t i = 0; i < (uint32_t)S.size(); ++i)
             if (!bit(gam[i], S[i])) { err = "internal: pivot order"; return BZ_ERANK; }
         const uint32_t W = (j < num_full) ? c.W_full : c.W_partial;
         c.packed_off.push_back(c.packed.size());
+        // the columns outside S_j, in ascending order
+        std::vector<uint32_t> rest;
+        for (uint32_t cc = 0; cc < n; ++cc) if (!in[cc]) rest.push_back(cc);
         for (uint32_t i = 0; i < k; ++i) {
             c.full_rows.push_back(gam[i]);
-            std::vector<uint32_t> words(W, 0);
-            uint32_t pos = 0;
-            for (uint32_t cc = 0; cc < n; ++cc) {
-                if (in[cc]) continue;
-                if (bit(gam[i], cc)) words[pos >> 5] |= 1u << (pos & 31);
-                ++pos;
-            }
-            c.packed.insert(c.packed.end(), words.begin(), words.end());
+            const size_t at = c.packed.size();
+            c.packed.resize(at + W, 0u);
+            for (uint32_t pos = 0; pos < (uint32_t)rest.size(); ++pos)
+                if (bit(gam[i], rest[pos])) c.packed[at + (pos >> 5)] |= 1u << (pos & 31);
         }
     }
     return BZ_OK;
