@@ -1063,7 +1063,14 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         {
             uint32_t g = next_g, j = next_j, Lw = L, Lc = Lcert;
             const uint32_t cap = use_sched ? 1u : window;
-            while (win.size() < cap && g <= k && !(opt.max_level && g > opt.max_level)) {
+            // a level small enough for its tasks to share a launch is not split
+            // across windows (up to the records' kChainMax)
+            auto more = [&]() {
+                if (win.size() < cap) return true;
+                return !use_sched && j != 0 && win.size() < kChainMax &&
+                       (double)bz::binom_sat(k, g) < kGroupMaxComb;
+            };
+            while (more() && g <= k && !(opt.max_level && g > opt.max_level)) {
                 Task t;
                 const bz_status e = make_task(j, g, t);
                 if (e != BZ_OK) return e;

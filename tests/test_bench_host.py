@@ -42,6 +42,23 @@ def test_small_level_threshold_matches_the_library():
     assert m and float(m.group(1)) == bench.SMALL_LEVEL_COMB
 
 
+def test_group_rule_matches_the_library():
+    # bench counts the dominant kernel's launches with the library's rule for
+    # the levels whose full-rank Gamma_j share a launch
+    api = open(os.path.join(ROOT, "paper_1911_08963_amd", "csrc", "bz_api.cpp")).read()
+    m = re.search(r"kGroupMaxComb\s*=\s*([0-9.]+)", api)
+    assert m and float(m.group(1)) == bench.GROUP_LEVEL_COMB
+    kh = open(os.path.join(ROOT, "paper_1911_08963_amd", "csrc", "bz_kernels.h")).read()
+    m = re.search(r"kMaxGroup\s*=\s*([0-9]+)", kh)
+    assert m and int(m.group(1)) == bench.GROUP_MAX
+    # [192,64], 3 full-rank sets: levels 5 (7.6e6 sums, small variant), 6 (7.5e7, one
+    # grouped launch), 7 and 8 (one launch per task)
+    stats = [(j, g, 0, 0, 0) for g in (5, 6, 7, 8) for j in range(3)]
+    assert bench.dominant_launches(stats, 64, 3) == 1 + 3 + 3
+    # a partial Gamma_m runs alone
+    assert bench.dominant_launches([(j, 6, 0, 0, 0) for j in range(3)], 64, 2) == 2
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
