@@ -326,10 +326,11 @@ __device__ uint32_t unrank_into(const uint64_t *binom, uint64_t r, uint32_t t, u
 // (OneTask list, fixed by the host). Each task's tiles are dealt to the waves
 // round-robin; every wave keeps its key, combination count and statistics word
 // in LDS; after a barrier wave 0 merges them and applies Alg. 1's bookkeeping
-// (the step kernel's rules), and after a second barrier the waves go on with
-// the next task or leave. When the search is over wave 0 finds the witness in
-// the winning tile. Nothing but LDS and the final records is written, and no
-// device-scope atomic is needed. Larger levels go on as one launch per task.
+// (the rules of the enumeration kernel's step), and after a second barrier the
+// waves go on with the next task or leave. When the search is over the four
+// waves find the witness in the winning tile. Nothing but LDS and the final
+// records is written, and no device-scope atomic is needed. Larger levels go
+// on as launches of the enumeration kernel.
 
 template <bool STATS>
 __device__ __forceinline__ void one_tile(const OneArgs &a, const OneTask &T, uint64_t tile, uint32_t lane,
@@ -374,7 +375,7 @@ __device__ __forceinline__ void one_tile(const OneArgs &a, const OneTask &T, uin
 // tile (one wave), then the XOR of its full rows.
 __device__ bool one_witness(const OneArgs &a, const OneTask &T, uint64_t tile, uint32_t U, uint32_t lane,
                             cptr64 binom_c, const uint64_t *sb, uint32_t bt, const uint32_t *lrows,
-                            uint64_t (&cw)[kHostWords]) {
+                            uint64_t (&cw)[kHostWords], uint32_t s_first, uint32_t s_step, const uint32_t *stop) {
     const bool partial = T.j >= a.m_f;
     const uint32_t *rows = (const uint32_t *)uni64((uint64_t)(a.rows + T.row_off));
     TaskArgs t{};
@@ -394,7 +395,8 @@ __device__ bool one_witness(const OneArgs &a, const OneTask &T, uint64_t tile, u
     switch (T.W) {
 #define BZ_FIND(WW)                                                                                          \
     case WW:                                                                                                 \
-        found = find_in_tile<WW, slots_for_w(WW)>(t, rc, binom_c, srow, sb, bt, rp, tile, lane, U, g, q, h); \
+        found = find_in_tile<WW, slots_for_w(WW)>(t, rc, binom_c, srow, sb, bt, rp, tile, lane, U, g, q, h, \
+                                                  s_first, s_step, stop);                                   \
         break;
         BZ_FIND(1) BZ_FIND(2) BZ_FIND(3) BZ_FIND(4) BZ_FIND(5) BZ_FIND(6) BZ_FIND(7) BZ_FIND(8)
 #undef BZ_FIND
@@ -550,22 +552,36 @@ __global__ __launch_bounds__(kBlock) void bz_one_kernel(const OneArgs *__restric
             }
         }
     }
-    if (wv == 0) {
-        uint32_t wit = 0;
-        if (status == kOneStopped && run.want_witness && have_best) {
-            uint64_t cw[kHostWords] = {0, 0, 0, 0};
-            const bool ok = one_witness(a, one_task(a.tasks + best_task), best_tile, U, lane, binom_c, sb, bt,
-                                        lrows, cw);
-            wit = ok ? 1u : 2u;
-            if (lane == 0)
+    // The witness: the four waves share the winning tile's slots (wave w takes
+    // slots w, w + 4, ...); the first to find a combination of weight U writes
+    // it, and the others leave their search at their next slot.
+    __shared__ uint32_t wit_share[5];                  // status, U, have_best, best_task, found
+    __shared__ unsigned long long wit_tile;
+    if (wv == 0 && lane == 0) {
+        wit_share[0] = status; wit_share[1] = U; wit_share[2] = have_best; wit_share[3] = best_task;
+        wit_share[4] = 0;
+        wit_tile = best_tile;
+    }
+    __syncthreads();
+    if (uni(wit_share[0]) == kOneStopped && run.want_witness && uni(wit_share[2])) {
+        uint64_t cw[kHostWords] = {0, 0, 0, 0};
+        const bool ok = one_witness(a, one_task(a.tasks + uni(wit_share[3])), uni64(wit_tile), uni(wit_share[1]),
+                                    lane, binom_c, sb, bt, lrows, cw, wv, kWaves, &wit_share[4]);
+        if (ok) {
+            uint32_t won = 0;
+            if (lane == 0) won = atomicCAS(&wit_share[4], 0u, 1u) == 0u ? 1u : 0u;
+            if (uni(won) && lane == 0)
                 for (int w = 0; w < kHostWords; ++w) S->witness[w] = cw[w];
         }
-        if (lane == 0) {
-            S->wit_flag = wit;
-            S->U = U; S->L = L; S->Lcert = Lcert; S->status = status; S->ntasks = ntasks;
-            S->have_best = have_best; S->best_task = best_task; S->best_tile = best_tile;
-            S->combinations = combos;
-        }
+    }
+    __syncthreads();
+    if (wv == 0 && lane == 0) {
+        uint32_t wit = 0;
+        if (status == kOneStopped && run.want_witness && have_best) wit = wit_share[4] ? 1u : 2u;
+        S->wit_flag = wit;
+        S->U = U; S->L = L; S->Lcert = Lcert; S->status = status; S->ntasks = ntasks;
+        S->have_best = have_best; S->best_task = best_task; S->best_tile = best_tile;
+        S->combinations = combos;
     }
 }
 

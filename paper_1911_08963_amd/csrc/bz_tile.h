@@ -549,7 +549,9 @@ __device__ __forceinline__ void run_tile(const TaskArgs &a, cptr32 rows, cptr64 
 
 // Finds one combination of the tile whose weight is target (the tile is
 // known to hold one). The lane subsets are taken one slot at a time (slot s of
-// lane block b: ranks b * 64 * SLOTS + lane * SLOTS + s), each against a walk over the tile's
+// lane block b: ranks b * 64 * SLOTS + lane * SLOTS + s; slots s_first,
+// s_first + s_step, ... when several waves share the search, each leaving once
+// the work-group's stop word is set), each against a walk over the tile's
 // heads; after each head step a ballot tells whether any lane hit. Returns
 // (uniform) true and, in every lane, the lane-subset rank and head rank of the
 // first hit. Few registers: this runs inside the resident serving kernel.
@@ -557,13 +559,18 @@ template <int W, int SLOTS>
 __device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cptr64 binom_c,
                                              const uint32_t *srow, const uint64_t *sbin, uint32_t bt,
                                              cptr_rect rect_p, uint64_t tile, uint32_t lane, uint32_t target,
-                                             TileGeom &t, uint64_t &q_hit, uint64_t &h_hit) {
+                                             TileGeom &t, uint64_t &q_hit, uint64_t &h_hit, uint32_t s_first = 0,
+                                             uint32_t s_step = 1, const uint32_t *stop = nullptr) {
     t = locate_tile(a.nrects, rect_p, tile);
     const uint64_t h0 = t.hb * a.heads_per_tile;
     const uint64_t count = umin64(h0 + a.heads_per_tile, t.head_count) - h0;
     bool found = false;
     const uint64_t nslots = (uint64_t)t.lane_mult * SLOTS;
-    for (uint64_t s = 0; s < nslots && !found; ++s) {
+    float lf_top = 0.f;                            // log2(lane_t!)
+    for (uint32_t j = 2; j <= t.lane_t; ++j) lf_top += __builtin_amdgcn_logf((float)j);
+    for (uint64_t s = s_first; s < nslots && !found; s += s_step) {
+        // another wave of the work-group has found one (stop: an LDS word)
+        if (stop && uni(__hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))) break;
         // slot s % SLOTS of lane block s / SLOTS of the tile
         const uint64_t base = (t.lb * t.lane_mult + s / SLOTS) * (kWaveSize * SLOTS) + s % SLOTS;
         if (base >= t.lane_count) break;                // lane 0 past the end: every lane is
@@ -576,13 +583,16 @@ __device__ __forceinline__ bool find_in_tile(const TaskArgs &a, cptr32 rows, cpt
         {
             uint64_t r = valid ? q : 0ull;
             uint32_t hi = t.lane_n - 1;
+            float lf = lf_top;
             for (uint32_t i = t.lane_t; i >= 1; --i) {
-                uint32_t c = colex_digit(sbin, bt, i, i - 1, hi, r);
-                r -= sbin[c * bt + i];
+                uint64_t bc;
+                const uint32_t c = colex_digit_est(sbin, bt, i, hi, r, lf, bc);   // two look-ups, not a bisection
+                r -= bc;
                 const uint32_t row = t.lane_off + c;
 #pragma unroll
                 for (int w = 0; w < W; ++w) P[w] ^= srow[row * W + w];
                 low += (row < a.k_low) ? 1u : 0u;
+                lf -= __builtin_amdgcn_logf((float)i);
                 hi = c - 1;
             }
         }
