@@ -236,10 +236,16 @@ class SearchResult:
 _ws_cache = {}
 
 
+_ws_single = []
+
+
 def workspace_bytes() -> int:
-    b = ctypes.c_size_t()
-    _check(lib().bz_workspace_bytes(None, 0, None, ctypes.byref(b)))
-    return b.value
+    """bz_workspace_bytes of a single search (the same for every code: asked once)."""
+    if not _ws_single:
+        b = ctypes.c_size_t()
+        _check(lib().bz_workspace_bytes(None, 0, None, ctypes.byref(b)))
+        _ws_single.append(b.value)
+    return _ws_single[0]
 
 
 def _workspace(device, nbytes):

@@ -491,6 +491,31 @@ bool build_one_launch(bz_code &c, std::vector<bz::Rect> &rects, std::string &err
     c.one_plan_of.clear();
     const uint32_t k = c.k, last_j = c.nsets - 1;
     if (k == c.n) return true;                       // d = 1 without any enumeration
+    // The one launch pays off when its levels end the search; otherwise the
+    // search waits for it before its first window. It can end the search only if
+    // d is at most the bound its last level certifies. Against the weight where a
+    // random [n, k] code expects its first nonzero codeword (sum over w' <= w of
+    // C(n, w') 2^(k - n) reaches 1), allowing two below: a speed choice only,
+    // the result is the same either way. When it does not pay off, no one
+    // launch is prepared at all.
+    {
+        uint32_t g_last = 0;
+        for (uint32_t g = 1; g <= k && g <= (uint32_t)bz::kBinomT; ++g) {
+            if ((double)bz::binom_sat(k, g) > bz::kOneLaunchComb) break;
+            if ((g - 1) * c.nsets + c.nsets > bz::kOneMaxTasks) break;
+            g_last = g;
+        }
+        if (g_last == 0) return true;
+        double acc = 0.0;
+        uint32_t w_est = 0;
+        while (w_est < c.n && acc < 1.0) {
+            ++w_est;
+            acc += std::exp(std::lgamma((double)c.n + 1) - std::lgamma((double)w_est + 1) -
+                            std::lgamma((double)(c.n - w_est) + 1) + ((double)k - (double)c.n) * std::log(2.0));
+        }
+        c.one_likely = certified(last_j, g_last, c.num_full, c.partial_rank, k) + 2 >= w_est;
+        if (!c.one_likely) return true;
+    }
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> plan_index;   // (g, slots) -> index in one_plans
     for (uint32_t g = 1; g <= k && g <= (uint32_t)bz::kBinomT; ++g) {
         if ((double)bz::binom_sat(k, g) > bz::kOneLaunchComb) break;
@@ -541,22 +566,6 @@ bool build_one_launch(bz_code &c, std::vector<bz::Rect> &rects, std::string &err
     std::vector<uint32_t> first(c.one_plans.size(), 0);
     for (size_t pi = 1; pi < c.one_plans.size(); ++pi) first[pi] = first[pi - 1] + (uint32_t)c.one_plans[pi - 1].rects.size();
     for (size_t t = 0; t < c.one_tasks.size(); ++t) c.one_tasks[t].rect_off = first[c.one_plan_of[t]];
-    // The one launch pays off when its levels end the search; otherwise the
-    // search waits for it before its first window. It can end the search only if
-    // d is at most the bound its last level certifies. Against the weight where a
-    // random [n, k] code expects its first nonzero codeword (sum over w' <= w of
-    // C(n, w') 2^(k - n) reaches 1), allowing two below: a speed choice only,
-    // the result is the same either way.
-    if (!c.one_tasks.empty()) {
-        double acc = 0.0;
-        uint32_t w_est = 0;
-        while (w_est < c.n && acc < 1.0) {
-            ++w_est;
-            acc += std::exp(std::lgamma((double)c.n + 1) - std::lgamma((double)w_est + 1) -
-                            std::lgamma((double)(c.n - w_est) + 1) + ((double)k - (double)c.n) * std::log(2.0));
-        }
-        c.one_likely = c.one_tasks.back().cert_level + 2 >= w_est;
-    }
     return true;
 }
 
@@ -1246,6 +1255,10 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
             ra.ntasks = (uint32_t)win.size();
             ra.U0 = U_start;
             ra.have0 = have_start ? 1u : 0u;
+            ra.k = k;
+            uint32_t gmax = 0;
+            for (const Task &t : win) gmax = std::max(gmax, t.g);
+            if ((size_t)(k + 1) * (gmax + 1) * sizeof(uint64_t) <= 32 * 1024) ra.lds_g = gmax;
             BZ_HIP(bz::launch_recover_window(ra, rec_threads, st));
         }
         BZ_HIP(hipMemcpyAsync(words, ws + kWsChain, 128 + win.size() * kRecBytes, hipMemcpyDeviceToHost, st));

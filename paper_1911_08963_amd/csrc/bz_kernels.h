@@ -111,6 +111,8 @@ struct RecoverWindowArgs {
     uint32_t ntasks;
     uint32_t U0;                         // the upper bound when the window started
     uint32_t have0;                      // a winning tile was known when the window started
+    uint32_t k;
+    uint32_t lds_g;                      // binomials with y <= lds_g staged in LDS (0: read from binom)
     uint32_t _pad;
 };
 

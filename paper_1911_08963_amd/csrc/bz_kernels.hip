@@ -195,7 +195,9 @@ __global__ void bz_chain_init_kernel(unsigned long long *records, uint32_t n, Ch
 // to the rows of the tile's prefix task when it has one. The first thread
 // whose combination has the target weight writes its row indices and the
 // codeword (XOR of the full rows, original coordinates).
-__device__ void recover_tile(const RecoverArgs &a, uint64_t id) {
+// bn, bstride: the binomials C(x, y) at bn[x * bstride + y] (the device table,
+// or a work-group's copy in LDS).
+__device__ void recover_tile(const RecoverArgs &a, uint64_t id, const uint64_t *bn, uint32_t bstride) {
     const Rect R = a.rect;
     // the tile's lane subsets: lane_mult blocks of 64 * slots
     const uint64_t lane_items = (uint64_t)kWaveSize * a.slots * (R.lane_mult ? R.lane_mult : 1u);
@@ -216,9 +218,9 @@ __device__ void recover_tile(const RecoverArgs &a, uint64_t id) {
             uint32_t lo = i - 1, c = hi;
             while (lo < c) {
                 uint32_t mid = (lo + c + 1) >> 1;
-                if (a.binom[mid * (kBinomT + 1) + i] <= r) lo = mid; else c = mid - 1;
+                if (bn[mid * bstride + i] <= r) lo = mid; else c = mid - 1;
             }
-            r -= a.binom[lo * (kBinomT + 1) + i];
+            r -= bn[lo * bstride + i];
             const uint32_t row = off + lo;
             idx[cnt++] = row;
             for (uint32_t w = 0; w < a.W; ++w) word[w] ^= a.rows[row * a.W + w];
@@ -248,7 +250,7 @@ __device__ void recover_tile(const RecoverArgs &a, uint64_t id) {
 }
 
 __global__ void bz_recover_kernel(RecoverArgs a) {
-    recover_tile(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    recover_tile(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, a.binom, kBinomT + 1);
 }
 
 // The window's winning task, by the host's rule (the first task whose minimum
@@ -257,6 +259,19 @@ __global__ void bz_recover_kernel(RecoverArgs a) {
 // is one of its tasks: then the host recovers the witness itself.
 __global__ void bz_recover_window_kernel(RecoverWindowArgs a) {
     if (!a.state->done) return;
+    // the binomials C(x, y), x <= k, y <= lds_g, in LDS when the launch has room
+    extern __shared__ uint64_t rbin[];
+    const uint64_t *bn = a.binom;
+    uint32_t bstride = kBinomT + 1;
+    if (a.lds_g) {
+        bstride = a.lds_g + 1;
+        for (uint32_t i = threadIdx.x; i < (a.k + 1) * bstride; i += blockDim.x) {
+            const uint32_t x = i / bstride, y = i - x * bstride;
+            rbin[i] = a.binom[x * (kBinomT + 1) + y];
+        }
+        __syncthreads();
+        bn = rbin;
+    }
     uint32_t U = a.U0;
     bool have = a.have0 != 0;
     int best = -1;
@@ -298,7 +313,7 @@ __global__ void bz_recover_window_kernel(RecoverWindowArgs a) {
     const uint64_t n = (uint64_t)kWaveSize * T.slots * (r.rect.lane_mult ? r.rect.lane_mult : 1u) * T.heads_per_tile;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += stride) {
-        recover_tile(r, id);
+        recover_tile(r, id, bn, bstride);
         if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     }
 }
@@ -373,7 +388,8 @@ hipError_t launch_chain_init(unsigned long long *records, uint32_t n, ChainState
 
 hipError_t launch_recover_window(const RecoverWindowArgs &a, uint64_t threads, hipStream_t st) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((threads + 255) / 256, 2048);
-    hipLaunchKernelGGL(bz_recover_window_kernel, dim3(grid), dim3(256), 0, st, a);
+    const size_t lds = a.lds_g ? (size_t)(a.k + 1) * (a.lds_g + 1) * sizeof(uint64_t) : 0;
+    hipLaunchKernelGGL(bz_recover_window_kernel, dim3(grid), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
