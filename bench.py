@@ -44,10 +44,10 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # of the dominant kernel (the 15 working launches of a search on levels of at
 # least 2^24 sums). With 16 lane sums per lane they are register spills of the
 # lane setup written back, not data: the algorithmic bytes are 0.
-ENUM_TRAFFIC = {"sources_sha256_16": "63374d55b98b7885", "workload": "plain192",
-                "kib_per_launch": {(16, 4): (8918.4, 51239.5), (16, 8): (8938.03, 52175.37),
-                                   (16, 16): (8999.75, 55249.33), (8, 8): (190.60, 112.21),
-                                   (8, 4): (190.19, 112.15)}}
+ENUM_TRAFFIC = {"sources_sha256_16": "2d53dc6186b025c8", "workload": "plain192",
+                "kib_per_launch": {(16, 4): (8911.68, 51236.77), (16, 8): (8935.26, 52164.55),
+                                   (16, 16): (8995.60, 55221.91), (8, 8): (189.24, 112.25),
+                                   (8, 4): (188.92, 112.26)}}
 
 
 def enum_traffic_bytes(workload: str, tuned) -> float | None:
