@@ -66,24 +66,44 @@ SMALL_LEVEL_COMB = 1 << 24
 # (the library's rule); above it every task is a launch of its own.
 GROUP_LEVEL_COMB = 1 << 27
 GROUP_MAX = 4
+LEVEL_GROUP_MAX = 8
 
 
 def dominant_launches(stats, k: int, m_f: int) -> int:
-    """Launches of the dominant enumeration variant (levels of at least 2^24 sums) that
-    a search with these per-task records made: one per task from 2^27 sums up, below
-    that one per group of up to GROUP_MAX full-rank tasks of a level plus one per
-    partial task. Launches enqueued past the stop return at once and are not counted."""
-    n = 0
-    per_level = {}
-    for s in stats:
+    """Launches of the dominant enumeration variant (levels of at least 2^24 sums, 16
+    lane sums per lane: W <= 4) that a search with these per-task records (in Alg. 1's
+    order) made, by the library's rule: one per task from 2^27 sums up and per partial
+    task; below that, consecutive full-rank tasks share a launch, up to LEVEL_GROUP_MAX
+    when they span a level's end, else up to GROUP_MAX of one level (the library's
+    shared-memory and window limits never bind on the bench's workloads). Launches
+    enqueued past the stop return at once and are not counted."""
+    recs = list(stats)
+
+    def groupable(s):
         cb = math.comb(k, s[1])
-        if cb < SMALL_LEVEL_COMB:
+        return SMALL_LEVEL_COMB <= cb < GROUP_LEVEL_COMB and s[0] < m_f
+
+    n = p = 0
+    while p < len(recs):
+        s = recs[p]
+        if math.comb(k, s[1]) < SMALL_LEVEL_COMB:
+            p += 1
             continue
-        if cb >= GROUP_LEVEL_COMB or s[0] >= m_f:
-            n += 1
-        else:
-            per_level[s[1]] = per_level.get(s[1], 0) + 1
-    return n + sum(-(-x // GROUP_MAX) for x in per_level.values())
+        n += 1
+        if not groupable(s):
+            p += 1
+            continue
+        span = 1
+        while span < LEVEL_GROUP_MAX and p + span < len(recs) and groupable(recs[p + span]):
+            span += 1
+        if recs[p + span - 1][1] != s[1]:
+            p += span
+            continue
+        grp = 1
+        while grp < GROUP_MAX and p + grp < len(recs) and groupable(recs[p + grp]) and recs[p + grp][1] == s[1]:
+            grp += 1
+        p += grp
+    return n
 KERNEL_SOURCES = ("bz_kernels.hip", "bz_tile.h", "bz_kernels.h", "bz_internal.h", "bz_plan.cpp")
 
 

@@ -111,7 +111,9 @@ enum {
     BZ_F_LEVEL_STOP = 2u,   /* check L >= U once per level (Alg. 1 as printed)                 */
     BZ_F_NO_WITNESS = 4u,   /* skip witness recovery                                           */
     BZ_F_TASK_LAUNCHES = 8u /* bz_min_distance: one launch per task on every level (by default the
-                               levels of at most 2^31 sums run in one launch); EINVAL elsewhere  */
+                               levels of at most 4096 sums run in one launch of one work-group,
+                               and consecutive full-rank tasks of levels below 2^27 sums that
+                               use the same kernel variant share launches); EINVAL elsewhere */
 };
 
 typedef struct {

@@ -1165,9 +1165,60 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
         for (size_t i = 0; i < win.size(); ++i) {
             const Task &t = win[i];
             unsigned long long *rec = d_records + i * bz::kRecWords;
-            // consecutive full-rank tasks of a small level share one launch
+            // consecutive full-rank tasks of small levels that run the same
+            // kernel variant share one launch: up to kMaxLevelTasks when they
+            // span a level's end, else up to kMaxGroup of the one level
+            const bool grouping = !(opt.flags & BZ_F_TASK_LAUNCHES);
+            auto groupable = [&](const Task &u) {
+                return !u.sp && u.j < m_f && (double)bz::binom_sat(k, u.g) < kGroupMaxComb && u.W == t.W &&
+                       u.slots == t.slots;
+            };
+            uint32_t span = 1, gmax = t.g;
+            if (grouping && groupable(t))
+                while (span < bz::kMaxLevelTasks && i + span < win.size() && groupable(win[i + span]) &&
+                       bz::enum_lds_bytes(k, std::max(gmax, win[i + span].g), t.W, span + 1) <= 65536)
+                    gmax = std::max(gmax, win[i + span++].g);
+            if (span > 1 && win[i + span - 1].g != t.g) {
+                bz::LevelsArgs la{};
+                bz::TaskArgs &a = la.t;
+                a.rows = (const uint32_t *)c->dev;
+                a.binom = dc.binom;
+                a.rects = d_rects;
+                a.key = rec + bz::kRecKey; a.stats = rec + bz::kRecStats; a.ncomb = rec + bz::kRecNcomb;
+                a.tile_ctr = rec + bz::kRecCtr;
+                a.cancel = (const uint32_t *)opt.cancel;
+                a.k = k; a.k_low = c->k_low(t.j); a.g = gmax;
+                a.chain = d_state;
+                la.ntasks = span;
+                uint64_t tiles = 0;
+                for (uint32_t q = 0; q < span; ++q) {
+                    const Task &u = win[i + q];
+                    la.row_off[q] = (uint32_t)c->packed_off[u.j];
+                    la.rect_off[q] = (uint32_t)on_device.at(u.key);
+                    la.g[q] = u.g;
+                    la.nrects[q] = (uint32_t)u.plan->rects.size();
+                    la.heads[q] = u.plan->heads_per_tile;
+                    tiles += u.plan->total_tiles;
+                    la.tile_end[q] = tiles;
+                    la.totals[q] = bz::binom_sat(k, u.g);
+                    la.cert_task[q] = certified(u.j, u.g, m_f, k_m, k);
+                    la.cert_level[q] = level_bound(u.g);
+                    if (u.j == last_j) la.last_mask |= 1u << q;
+                }
+                a.total_tiles = tiles;
+                bz::ChainStep &cs = a.step;
+                cs.state = d_state;
+                cs.level_stop = level_stop;
+                cs.stats = stats;
+                const uint32_t grid = (uint32_t)std::max<uint64_t>(
+                    1, std::min<uint64_t>((tiles + 3) / 4, (uint64_t)dc.cus * 8));
+                if (i == 0 && ev0) BZ_HIP(hipEventRecord(ev0, st));
+                BZ_HIP(bz::launch_enum_levels(la, t.W, t.slots, stats, grid, st));
+                i += span - 1;
+                continue;
+            }
             uint32_t group = 1;
-            if (!t.sp && t.j < m_f && (double)bz::binom_sat(k, t.g) < kGroupMaxComb)
+            if (grouping && groupable(t))
                 while (group < bz::kMaxGroup && i + group < win.size() && !win[i + group].sp &&
                        win[i + group].g == t.g && win[i + group].j == t.j + group && win[i + group].j < m_f &&
                        win[i + group].key == t.key && bz::enum_lds_bytes(k, t.g, t.W, group + 1) <= 65536)

@@ -71,6 +71,28 @@ struct TaskArgs {
     uint32_t last_mask;
 };
 
+// Consecutive tasks of several levels in one launch (bz_enum_levels_kernel).
+constexpr uint32_t kMaxLevelTasks = 8;
+
+// A group of consecutive tasks in Alg. 1's order, spanning level ends: all
+// full rank, all of one kernel variant. t carries what they share (binomials,
+// k, bounds, cancel word, the step's state and flags), with t.rows the packed
+// rows' base, t.rects the tilings' base, t.key the first task's record (task i's
+// is kRecWords words further), t.g the largest level and t.total_tiles the sum.
+// Task i: rows at t.rows + row_off[i], rectangles at t.rects + rect_off[i]
+// (nrects[i] of them, heads[i] heads per tile), level g[i], tiles
+// [tile_end[i-1], tile_end[i]) of the launch; its step has total = totals[i],
+// cert_task = cert_task[i], cert_level = cert_level[i] and last_of_level =
+// bit i of last_mask.
+struct LevelsArgs {
+    TaskArgs t;
+    uint32_t ntasks, last_mask;
+    uint32_t row_off[kMaxLevelTasks], rect_off[kMaxLevelTasks];
+    uint32_t g[kMaxLevelTasks], nrects[kMaxLevelTasks], heads[kMaxLevelTasks];
+    uint32_t cert_task[kMaxLevelTasks], cert_level[kMaxLevelTasks];
+    uint64_t tile_end[kMaxLevelTasks], totals[kMaxLevelTasks];
+};
+
 struct RecoverArgs {
     const uint32_t *rows;        // packed rows of Gamma_j
     const uint64_t *full_rows;   // k x kHostWords full rows of Gamma_j
@@ -331,6 +353,10 @@ constexpr size_t kBatchLdsMax = 24 * 1024;
 hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool partial, bool stats,
                        uint32_t grid, hipStream_t st);
 size_t enum_lds_bytes(uint32_t k, uint32_t g, uint32_t W, uint32_t group = 1);
+// A group of tasks spanning levels (full rank, W <= 8, the variant's slots);
+// the shared memory is enum_lds_bytes(k, largest g, W, ntasks).
+hipError_t launch_enum_levels(const LevelsArgs &a, uint32_t W, uint32_t slots, bool stats, uint32_t grid,
+                              hipStream_t st);
 hipError_t launch_task_init(unsigned long long *key, unsigned long long *stats,
                             unsigned long long *ncomb, unsigned long long *ctr, hipStream_t st);
 // Resets n task records (kRecWords each), writes the window's starting bounds

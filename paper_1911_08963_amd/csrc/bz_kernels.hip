@@ -162,6 +162,126 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((STATS |
     }
 }
 
+// Consecutive tasks of several small levels in one launch (a group spanning
+// level ends, LevelsArgs): the same staging, tiles and bookkeeping as
+// bz_enum_kernel, with each task's tiling, level and step read from a table in
+// LDS once per tile. Tasks of a later level run before the earlier ones'
+// steps have been applied: with the bounds from before the launch, so they
+// may enumerate more than Alg. 1 would, never less, and their steps are
+// applied in order by the last work-group (a step after the stop does
+// nothing).
+template <int W, int SLOTS, bool STATS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 5))) void bz_enum_levels_kernel(LevelsArgs la) {
+    const TaskArgs &a = la.t;
+    if (a.chain->done) return;
+    const uint32_t u_prev = a.chain->U, exit_at = a.chain->exit_at;
+    extern __shared__ uint64_t smem[];
+    const uint32_t G = la.ntasks;
+    const uint32_t bt = a.g + 1;                          // largest level: binomial row stride in LDS
+    uint64_t *sbin = smem;                                // (k+1) x (g+1)
+    uint32_t *srows = (uint32_t *)(smem + (size_t)(a.k + 1) * bt);   // G x k x W
+    uint32_t *spxs = srows + (size_t)G * a.k * W;         // G x (k+1) x W prefix XORs
+    __shared__ uint64_t s_tile_end[kMaxLevelTasks];
+    __shared__ uint32_t s_task[kMaxLevelTasks][5];        // rectangles, level, rectangle count, heads, rows
+    for (uint32_t i = threadIdx.x; i < (a.k + 1) * bt; i += blockDim.x) {
+        uint32_t x = i / bt, y = i - x * bt;
+        sbin[i] = a.binom[x * (kBinomT + 1) + y];
+    }
+    for (uint32_t i = threadIdx.x; i < G * a.k * W; i += blockDim.x) {
+        const uint32_t ti = i / (a.k * W), r = i - ti * (a.k * W);
+        srows[i] = a.rows[la.row_off[ti] + r];
+    }
+    if (threadIdx.x < G) {
+        const uint32_t q = threadIdx.x;
+        s_tile_end[q] = la.tile_end[q];
+        s_task[q][0] = la.rect_off[q];
+        s_task[q][1] = la.g[q];
+        s_task[q][2] = la.nrects[q];
+        s_task[q][3] = la.heads[q];
+        s_task[q][4] = la.row_off[q];
+    }
+    __syncthreads();
+    for (uint32_t ti = 0; ti < G; ++ti) build_prefix_xor<W>(srows + ti * a.k * W, spxs + ti * (a.k + 1) * W, a.k);
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & (kWaveSize - 1);
+    cptr64 binom_c = (cptr64)a.binom;
+    const uint32_t waves_per_block = blockDim.x / kWaveSize;
+    const uint64_t first = (uint64_t)blockIdx.x * waves_per_block + uni(threadIdx.x / kWaveSize);
+    const uint64_t stride = (uint64_t)gridDim.x * waves_per_block;
+    __shared__ unsigned long long wave_words[kBlock / kWaveSize][kMaxLevelTasks][2];
+    const uint32_t wv = uni(threadIdx.x / kWaveSize);
+    if (lane == 0)
+        for (uint32_t ti = 0; ti < kMaxLevelTasks; ++ti) {
+            wave_words[wv][ti][0] = 0;
+            wave_words[wv][ti][1] = ~0ull;
+        }
+    TaskArgs t = a;
+    for (uint64_t it = first; it < a.total_tiles; it += stride) {
+        // the group's tasks take consecutive ranges of the launch's tiles
+        uint32_t ti = 0;
+        while (ti + 1 < G && it >= uni64(s_tile_end[ti])) ++ti;
+        const uint64_t tile = it - (ti ? uni64(s_tile_end[ti - 1]) : 0ull);
+        const cptr_rect rp = (cptr_rect)a.rects + uni(s_task[ti][0]);
+        t.g = uni(s_task[ti][1]);
+        t.nrects = uni(s_task[ti][2]);
+        t.heads_per_tile = uni(s_task[ti][3]);
+        t.rows = a.rows + uni(s_task[ti][4]);
+        if (a.cancel) {
+            uint32_t cv = __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (uni(cv) != 0u) break;
+        }
+        t.key = a.key + (size_t)ti * kRecWords;
+        t.ncomb = &wave_words[wv][ti][0];
+        t.stats = &wave_words[wv][ti][1];
+        if (exit_at) {
+            unsigned long long kv = __hip_atomic_load(t.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t cur = min((uint32_t)(kv >> kTileBits), u_prev);
+            if (uni(cur) <= exit_at) continue;
+        }
+        cptr32 rows = (cptr32)uni64((uint64_t)t.rows);
+        run_tile<W, SLOTS, false, STATS>(t, rows, binom_c, srows + ti * a.k * W, spxs + ti * (a.k + 1) * W, sbin,
+                                         bt, rp, tile, lane);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t ti = 0; ti < G; ++ti) {
+            unsigned long long nc = 0;
+            uint32_t smin = 0xffffffffu;
+            uint64_t scnt = 0;
+            for (uint32_t w = 0; w < kBlock / kWaveSize; ++w) {
+                nc += wave_words[w][ti][0];
+                const unsigned long long sw = wave_words[w][ti][1];
+                if (STATS && wave_words[w][ti][0] && sw != ~0ull) {
+                    const uint32_t m = (uint32_t)(sw >> kCountBits);
+                    if (m < smin) { smin = m; scnt = sw & kCountMask; }
+                    else if (m == smin) scnt += sw & kCountMask;
+                }
+            }
+            if (nc) {
+                atomicAdd(a.ncomb + (size_t)ti * kRecWords, nc);
+                if (STATS && smin != 0xffffffffu) stats_merge(a.stats + (size_t)ti * kRecWords, smin, scnt);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned long long left = atomicAdd(a.tile_ctr, 1ull);
+        if (left + 1 == gridDim.x) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            for (uint32_t ti = 0; ti < G; ++ti) {
+                ChainStep s = a.step;
+                s.key = a.key + (size_t)ti * kRecWords;
+                s.ncomb = a.ncomb + (size_t)ti * kRecWords;
+                s.total = la.totals[ti];
+                s.cert_task = la.cert_task[ti];
+                s.cert_level = la.cert_level[ti];
+                s.last_of_level = (la.last_mask >> ti) & 1u;
+                chain_step_apply(s, __hip_atomic_load(s.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                 __hip_atomic_load(s.ncomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+    }
+}
+
 // Resets a task's device words: key and statistics to "none", counters to 0.
 __global__ void bz_task_init_kernel(unsigned long long *key, unsigned long long *stats,
                                     unsigned long long *ncomb, unsigned long long *ctr) {
@@ -363,6 +483,44 @@ hipError_t launch_enum(const TaskArgs &a, uint32_t W, uint32_t slots, bool parti
     case 6: return launch_w<6>(a, slots, partial, stats, grid, lds, st);
     case 7: return launch_w<7>(a, slots, partial, stats, grid, lds, st);
     case 8: return launch_w<8>(a, slots, partial, stats, grid, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int W>
+static hipError_t launch_levels_w(const LevelsArgs &a, uint32_t slots, bool stats, uint32_t grid, size_t lds,
+                                  hipStream_t st) {
+#define BZ_LEVELS(S)                                                                                         \
+    do {                                                                                                     \
+        if (stats) hipLaunchKernelGGL((bz_enum_levels_kernel<W, S, true>), dim3(grid), dim3(kBlock), lds, st, a);  \
+        else hipLaunchKernelGGL((bz_enum_levels_kernel<W, S, false>), dim3(grid), dim3(kBlock), lds, st, a);        \
+        return hipGetLastError();                                                                            \
+    } while (0)
+    switch (slots) {
+    case 2: BZ_LEVELS(2);
+    case 4: BZ_LEVELS(4);
+    case 8: BZ_LEVELS(8);
+    case 16:
+        if constexpr (W <= 4) BZ_LEVELS(16);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+#undef BZ_LEVELS
+}
+
+hipError_t launch_enum_levels(const LevelsArgs &a, uint32_t W, uint32_t slots, bool stats, uint32_t grid,
+                              hipStream_t st) {
+    if (a.ntasks < 2 || a.ntasks > kMaxLevelTasks || !a.t.chain || !a.t.step.state) return hipErrorInvalidValue;
+    const size_t lds = enum_lds_bytes(a.t.k, a.t.g, W, a.ntasks);
+    switch (W) {
+    case 1: return launch_levels_w<1>(a, slots, stats, grid, lds, st);
+    case 2: return launch_levels_w<2>(a, slots, stats, grid, lds, st);
+    case 3: return launch_levels_w<3>(a, slots, stats, grid, lds, st);
+    case 4: return launch_levels_w<4>(a, slots, stats, grid, lds, st);
+    case 5: return launch_levels_w<5>(a, slots, stats, grid, lds, st);
+    case 6: return launch_levels_w<6>(a, slots, stats, grid, lds, st);
+    case 7: return launch_levels_w<7>(a, slots, stats, grid, lds, st);
+    case 8: return launch_levels_w<8>(a, slots, stats, grid, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
