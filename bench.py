@@ -44,10 +44,10 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # of the dominant kernel (the 15 working launches of a search on levels of at
 # least 2^24 sums). With 16 lane sums per lane they are register spills of the
 # lane setup written back, not data: the algorithmic bytes are 0.
-ENUM_TRAFFIC = {"sources_sha256_16": "2d53dc6186b025c8", "workload": "plain192",
-                "kib_per_launch": {(16, 4): (8911.68, 51236.77), (16, 8): (8935.26, 52164.55),
-                                   (16, 16): (8995.60, 55221.91), (8, 8): (189.24, 112.25),
-                                   (8, 4): (188.92, 112.26)}}
+ENUM_TRAFFIC = {"sources_sha256_16": "2055a62e14e4fd15", "workload": "plain192",
+                "kib_per_launch": {(16, 4): (8899.34, 51262.12), (16, 8): (8922.06, 52215.45),
+                                   (16, 16): (8983.04, 55241.33), (8, 8): (171.34, 100.29),
+                                   (8, 4): (170.95, 100.33)}}
 
 
 def enum_traffic_bytes(workload: str, tuned) -> float | None:

@@ -35,27 +35,42 @@ using ColVec = std::array<uint64_t, kHostWords>;   // a k-bit column, k <= 256
 
 inline bool bit(const HostRow &r, uint32_t c) { return (r[c >> 6] >> (c & 63)) & 1u; }
 
-int leading_bit(const ColVec &v) {
-    for (int w = kHostWords - 1; w >= 0; --w)
+// The highest set bit of the first kw words of v, or -1.
+int leading_bit(const ColVec &v, int kw) {
+    for (int w = kw - 1; w >= 0; --w)
         if (v[w]) return w * 64 + 63 - __builtin_clzll(v[w]);
     return -1;
 }
 
-// A GF(2) basis of k-bit vectors, one slot per leading bit.
+// A GF(2) basis of k-bit vectors, one slot per leading bit (vectors of
+// kw = ceil(k / 64) words; the words above are zero).
 struct XorBasis {
     std::vector<ColVec> slot;
     std::vector<char> used;
-    explicit XorBasis(uint32_t k) : slot(k), used(k, 0) {}
+    int kw;
+    explicit XorBasis(uint32_t k) : slot(k), used(k, 0), kw((int)((k + 63) / 64)) {}
     // Inserts v; returns true iff v was independent of the basis.
     bool insert(ColVec v) {
         for (;;) {
-            int lb = leading_bit(v);
+            int lb = leading_bit(v, kw);
             if (lb < 0) return false;
             if (!used[lb]) { slot[lb] = v; used[lb] = 1; return true; }
-            for (int w = 0; w < kHostWords; ++w) v[w] ^= slot[lb][w];
+            for (int w = 0; w < kw; ++w) v[w] ^= slot[lb][w];
         }
     }
 };
+
+// In-place transpose of a 64 x 64 bit matrix (bit c of a[r] <-> bit r of
+// a[c]): off-diagonal blocks of 32, then 16, ... 1 bits are swapped.
+void transpose64(uint64_t (&a)[64]) {
+    uint64_t m = 0x00000000FFFFFFFFull;
+    for (uint32_t j = 32; j != 0; j >>= 1, m ^= m << j)
+        for (uint32_t r = 0; r < 64; r = (r + j + 1) & ~j) {
+            const uint64_t t = ((a[r] >> j) ^ a[r + j]) & m;
+            a[r + j] ^= t;
+            a[r] ^= t << j;
+        }
+}
 
 // Reduced echelon form of rows under a column order (rows of nw words).
 // Returns the rank.
@@ -67,9 +82,10 @@ uint32_t reduce(std::vector<HostRow> &rows, const std::vector<uint32_t> &order, 
         while (p < k && !bit(rows[p], c)) ++p;
         if (p == k) continue;
         std::swap(rows[p], rows[r]);
+        // without branches on the data (random bits would mispredict half the time)
         for (uint32_t i = 0; i < k; ++i) {
-            if (i == r || !bit(rows[i], c)) continue;
-            for (uint32_t w = 0; w < nw; ++w) rows[i][w] ^= rows[r][w];
+            const uint64_t m = (uint64_t)0 - (uint64_t)(bit(rows[i], c) && i != r);
+            for (uint32_t w = 0; w < nw; ++w) rows[i][w] ^= rows[r][w] & m;
         }
         ++r;
     }
@@ -154,11 +170,14 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
     }
     // columns as k-bit vectors
     std::vector<ColVec> col(n);
-    for (uint32_t cc = 0; cc < n; ++cc) {
-        col[cc].fill(0);
-        for (uint32_t i = 0; i < k; ++i)
-            if (bit(rows[i], cc)) col[cc][i >> 6] |= 1ull << (i & 63);
-    }
+    for (uint32_t cc = 0; cc < n; ++cc) col[cc].fill(0);
+    for (uint32_t ib = 0; ib * 64 < k; ++ib)
+        for (uint32_t w = 0; w < nw; ++w) {
+            uint64_t a[64];
+            for (uint32_t r = 0; r < 64; ++r) a[r] = ib * 64 + r < k ? rows[ib * 64 + r][w] : 0;
+            transpose64(a);
+            for (uint32_t r = 0; r < 64 && w * 64 + r < n; ++r) col[w * 64 + r][ib] = a[r];
+        }
     const uint32_t trials = (opts && opts->perm_trials > 1) ? opts->perm_trials : 1;
     const uint64_t seed = opts ? opts->perm_seed : 0;
     SetChoice best = find_sets(col, k, scan_order(n, 0, seed));
@@ -201,7 +220,7 @@ bz_status prepare_host(const uint64_t *G, uint32_t k, uint32_t n, uint32_t ld,
             const size_t at = c.packed.size();
             c.packed.resize(at + W, 0u);
             for (uint32_t pos = 0; pos < (uint32_t)rest.size(); ++pos)
-                if (bit(gam[i], rest[pos])) c.packed[at + (pos >> 5)] |= 1u << (pos & 31);
+                c.packed[at + (pos >> 5)] |= (uint32_t)bit(gam[i], rest[pos]) << (pos & 31);
         }
     }
     return BZ_OK;
