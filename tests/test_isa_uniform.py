@@ -123,6 +123,9 @@ def test_enumeration_kernels_broadcast_in_uniform_loops(isa_asm):
     asm = isa_asm["bz_kernels.hip"]
     kernels, found = divergent_loops_with_broadcast(asm, r"^(_ZN2bz\d+bz_\w+_kernel\w*):")
     assert sum("bz_enum_kernel" in k for k in kernels) >= 64
+    # the launches of small-level tasks spanning level ends: W 1..8 x 2, 4, 8 slots
+    # (16 up to W = 4) x statistics or not
+    assert sum("bz_enum_levels_kernel" in k for k in kernels) == 56
     assert not found, found[:4]
 
 
