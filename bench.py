@@ -67,6 +67,7 @@ SMALL_LEVEL_COMB = 1 << 24
 GROUP_LEVEL_COMB = 1 << 27
 GROUP_MAX = 4
 LEVEL_GROUP_MAX = 8
+SPAN_MAX_COMB = 1 << 24
 
 
 def dominant_launches(stats, k: int, m_f: int) -> int:
@@ -74,7 +75,8 @@ def dominant_launches(stats, k: int, m_f: int) -> int:
     lane sums per lane: W <= 4) that a search with these per-task records (in Alg. 1's
     order) made, by the library's rule: one per task from 2^27 sums up and per partial
     task; below that, consecutive full-rank tasks share a launch, up to LEVEL_GROUP_MAX
-    when they span a level's end, else up to GROUP_MAX of one level (the library's
+    when they span a level's end (while the later levels' tasks hold at most
+    SPAN_MAX_COMB sums: never for this variant), else up to GROUP_MAX of one level (the library's
     shared-memory and window limits never bind on the bench's workloads). Launches
     enqueued past the stop return at once and are not counted."""
     recs = list(stats)
@@ -93,8 +95,12 @@ def dominant_launches(stats, k: int, m_f: int) -> int:
         if not groupable(s):
             p += 1
             continue
-        span = 1
+        span, later = 1, 0
         while span < LEVEL_GROUP_MAX and p + span < len(recs) and groupable(recs[p + span]):
+            if recs[p + span][1] != s[1]:
+                later += math.comb(k, recs[p + span][1])
+                if later > SPAN_MAX_COMB:
+                    break
             span += 1
         if recs[p + span - 1][1] != s[1]:
             p += span

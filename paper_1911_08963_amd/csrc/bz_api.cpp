@@ -127,6 +127,10 @@ std::shared_ptr<const bz::LevelPlan> cached_plan(uint32_t k, uint32_t g, uint32_
 // (up to bz::kMaxGroup of them): their launches are mostly fixed cost, and the
 // work a task past the stop still does there is small.
 constexpr double kGroupMaxComb = 134217728.0;   // 2^27
+// A launch of tasks spanning level ends runs the later levels' tasks with the
+// bounds from before the launch, even when an earlier task ends the search:
+// their sums together stay below this (about half a millisecond).
+constexpr double kSpanMaxComb = 16777216.0;     // 2^24
 
 // Lower bound certified once Gamma_0..Gamma_j are done at level g and the
 // later matrices at level g-1 (j == m_f is the partial matrix).
@@ -1174,10 +1178,18 @@ bz_status min_distance_impl(bz_code *c, const bz_opts *o, bz_result *res, const 
                        u.slots == t.slots;
             };
             uint32_t span = 1, gmax = t.g;
+            double later = 0;                    // sums of the tasks past the first task's level
             if (grouping && groupable(t))
                 while (span < bz::kMaxLevelTasks && i + span < win.size() && groupable(win[i + span]) &&
-                       bz::enum_lds_bytes(k, std::max(gmax, win[i + span].g), t.W, span + 1) <= 65536)
-                    gmax = std::max(gmax, win[i + span++].g);
+                       bz::enum_lds_bytes(k, std::max(gmax, win[i + span].g), t.W, span + 1) <= 65536) {
+                    const Task &u = win[i + span];
+                    if (u.g != t.g) {
+                        later += (double)bz::binom_sat(k, u.g);
+                        if (later > kSpanMaxComb) break;
+                    }
+                    gmax = std::max(gmax, u.g);
+                    ++span;
+                }
             if (span > 1 && win[i + span - 1].g != t.g) {
                 bz::LevelsArgs la{};
                 bz::TaskArgs &a = la.t;

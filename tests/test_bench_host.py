@@ -53,22 +53,33 @@ def test_group_rule_matches_the_library():
     assert m and int(m.group(1)) == bench.GROUP_MAX
     m = re.search(r"kMaxLevelTasks\s*=\s*([0-9]+)", kh)
     assert m and int(m.group(1)) == bench.LEVEL_GROUP_MAX
+    m = re.search(r"kSpanMaxComb\s*=\s*([0-9.]+)", api)
+    assert m and float(m.group(1)) == bench.SPAN_MAX_COMB
     # [192,64], 3 full-rank sets: levels 5 (7.6e6 sums, small variant), 6 (7.5e7, one
     # grouped launch), 7 and 8 (one launch per task)
     stats = [(j, g, 0, 0, 0) for g in (5, 6, 7, 8) for j in range(3)]
     assert bench.dominant_launches(stats, 64, 3) == 1 + 3 + 3
     # a partial Gamma_m runs alone
     assert bench.dominant_launches([(j, 6, 0, 0, 0) for j in range(3)], 64, 2) == 2
-    # k = 40: levels 7 (1.9e7 sums) and 8 (7.7e7) share one launch, 9 (2.7e8) does not
+    # k = 40: levels 7 (1.9e7 sums) and 8 (7.7e7) share launches within each level
+    # only (a later level's task is past the speculation cap), 9 (2.7e8) not at all
     stats = [(j, g, 0, 0, 0) for g in (6, 7, 8, 9) for j in range(2)]
-    assert bench.dominant_launches(stats, 40, 2) == 1 + 2
+    assert bench.dominant_launches(stats, 40, 2) == 1 + 1 + 2
     # a partial task in between ends a group
     assert bench.dominant_launches(stats, 40, 1) == 4 + 2
     # six full-rank sets: one level runs four tasks, then two, per launch
     assert bench.dominant_launches([(j, 6, 0, 0, 0) for j in range(6)], 64, 6) == 2
-    # across a level's end eight: six of level 7 and two of 8, then four of 8, then 9
     stats = [(j, g, 0, 0, 0) for g in (7, 8, 9) for j in range(6)]
-    assert bench.dominant_launches(stats, 40, 6) == 2 + 6
+    assert bench.dominant_launches(stats, 40, 6) == 2 + 2 + 6
+    # below the cap a group spans level ends (the rule itself, on small levels)
+    old = bench.SMALL_LEVEL_COMB
+    try:
+        bench.SMALL_LEVEL_COMB = 1
+        # k = 20, two sets: levels 2-4 (190, 1140, 4845 sums) in one launch of six tasks
+        stats = [(j, g, 0, 0, 0) for g in (2, 3, 4) for j in range(2)]
+        assert bench.dominant_launches(stats, 20, 2) == 1
+    finally:
+        bench.SMALL_LEVEL_COMB = old
 
 
 def test_more_than_one_gpu_is_refused():
