@@ -104,6 +104,29 @@ def test_small_random_codes(bz):
             _compare(bz, G, n, level_stop=True, tag=f"rand{t}-level")
 
 
+def test_stops_inside_level_spanning_launches(bz):
+    # [2k, k] codes with two full-rank sets and no leftover set, k = 26..40: the
+    # levels up to about 5 have below 2^21 sums, so consecutive tasks of several
+    # levels share one launch; the search stops after a task in the middle of
+    # such a launch (d odd: after Gamma_1 of a level), and the tasks after it,
+    # run with the bounds from before the launch, must not count
+    rng = np.random.default_rng(1911)
+    done = 0
+    while done < 12:
+        k = int(rng.integers(26, 41))
+        n = 2 * k
+        G = _rand(rng, n, k)
+        h = bz.Code(G, n, host_only=True)
+        sets = (h.num_full, h.partial_rank)
+        h.close()
+        if sets != (2, 0):
+            continue
+        _compare(bz, G, n, tag=f"span{done}")
+        if done % 3 == 0:
+            _compare(bz, G, n, level_stop=True, tag=f"span{done}-level")
+        done += 1
+
+
 def test_tilings_agree(bz):
     """Slots 2/4/8 and tiny head blocks (many tiles, many colex carries) give identical results."""
     rng = np.random.default_rng(7)
