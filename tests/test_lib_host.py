@@ -96,6 +96,15 @@ def test_prepare_matches_oracle_bit_exact():
                 got = np.unpackbits(words.view(np.uint8), bitorder="little")
                 assert np.array_equal(got, want)
     assert seen_partial > 30
+    # k above 128: the column vectors are built from three or four 64-row blocks
+    for t in range(12):
+        n = int(rng.integers(150, 257))
+        k = int(rng.integers(129, n + 1))
+        G = _rand(rng, n, k, bool(t % 2))
+        soc, mf, km, gam, _ = bz.prepare_host(G, n)
+        soc2, mf2, km2, gam2 = oracle.prepare(G, n)
+        assert (mf, km) == (mf2, km2)
+        assert np.array_equal(soc, soc2) and np.array_equal(gam, gam2)
 
 
 def test_prepare_plain_workloads():
